@@ -1,0 +1,107 @@
+/*
+ * FP64 CPU oracle for the coevolutionary traveltime-parameter search
+ * (arXiv 2304.11399).  TEST INFRASTRUCTURE ONLY: the tests, the smoke check
+ * and the benchmark's CPU-baseline leg call it; the product library never
+ * links, loads or calls anything here, and nothing here includes a header of
+ * the product.
+ *
+ * Plain, slow, obviously-correct definitions in double precision.  Parameter
+ * vectors of the evolutionary search are held in binary32 with every update
+ * written out in binary32 operations (no fused multiply-add), because the
+ * evolution's integer decisions (repair, crossover, argmax) must be taken in
+ * the same precision as the device path; every semblance value is binary64.
+ */
+#ifndef ENS_ORACLE_H
+#define ENS_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* A CMP-sorted prestack line plus the semblance configuration.
+ * Section "Traveltime parameter search": f(p) = S(p; #data, #config) where
+ * #data is the traces and geometry and #config the window, aperture and the
+ * initial coordinate t0 (eq. Sf). */
+typedef struct {
+    const double *u;        /* [n_tr][nt] trace samples, sample n at time n*dt */
+    int64_t n_tr;
+    int32_t nt;
+    double dt;
+    const int64_t *cmp_ptr; /* [n_cmp+1] CSR row pointer, traces sorted by (CMP, offset) */
+    int32_t n_cmp;
+    double dx;              /* CMP spacing (m) */
+    const double *offset;   /* [n_tr] full source-receiver offset h (m) */
+    int32_t half_w;         /* window is 2*half_w+1 samples centred on the traveltime */
+    int32_t op;             /* 1: CMP t^2 = t0^2 + C h^2 ; 3: CRS (A, B, C) */
+    int32_t ap_lo, ap_hi;   /* midpoint half-aperture (CMPs) at t index 0 and nt-1 */
+} or_line;
+
+typedef struct {
+    float lo[3], hi[3];
+    uint32_t inv_t0_mask;   /* bit d: bound d is given for p_d*t0, divide by max(t0, dt) */
+} or_bounds;
+
+typedef struct {
+    int32_t np_lo, np_hi;   /* NP_f at t index 0 and nt-1, linear in between */
+    int32_t ng_f;           /* NG_f */
+    int32_t np_bf, ng_bf;   /* NP_bf, NG_bf */
+    int32_t n_cycle;        /* N_cycle */
+    int32_t n_bucket;       /* traces per interactive domain */
+    int32_t ens_enabled;    /* 0: every sample runs on its own (plain DE) */
+    int32_t inject;         /* ENS sweep only: 0 disables every exchange of individuals */
+    float F, CR;
+    int32_t objective;      /* 0 semblance; 1 sphere mock; 2 needle mock */
+} or_de_cfg;
+
+/* counter-based generator: Philox-4x64 with 10 rounds (Salmon et al., SC'11) */
+void or_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+
+int32_t or_aperture(const or_line *L, int32_t n0);
+int32_t or_pop_size(const or_de_cfg *cfg, int32_t nt, int32_t n0);
+void or_sample_bounds(const or_line *L, const or_bounds *B, int32_t n0, float lo[3], float hi[3]);
+
+/* Semblance of parameter vector p at ZO sample (CMP j, time index n0).
+ * M_out: participating traces; margin_out: distance (samples) of the closest
+ * aperture trace from a participation boundary. */
+double or_semblance(const or_line *L, int32_t j, int32_t n0, const double *p,
+                    int32_t *M_out, double *margin_out);
+void or_semblance_batch(const or_line *L, int64_t n, const int32_t *cmp, const int32_t *t,
+                        const double *params, double *S, int32_t *M, double *margin);
+/* Gradient dS/dp (M held fixed, right derivative at integer traveltime). */
+double or_semblance_grad(const or_line *L, int32_t j, int32_t n0, const double *p, double *g);
+void or_semblance_grad_batch(const or_line *L, int64_t n, const int32_t *cmp, const int32_t *t,
+                             const double *params, double *S, double *grad);
+
+/* One generation's trial vectors from explicit generator words.
+ * pop, trial: [np][P]; S: [np]; words: [np][4] (the four 64-bit outputs). */
+void or_de_trial(int32_t np, int32_t P, const float *pop, const double *S, const uint64_t *words,
+                 float F, float CR, const float *lo, const float *hi, float *trial);
+
+/* Whole search.  cmp_out: [n_out] output CMPs; time indices [t_begin, t_end).
+ * params_out: [n_out][n_t][P]; S_out: [n_out][n_t].  Returns evaluations. */
+int64_t or_search(const or_line *L, const or_bounds *B, const or_de_cfg *cfg, uint64_t seed,
+                  const int32_t *cmp_out, int32_t n_out, int32_t t_begin, int32_t t_end,
+                  float *params_out, double *S_out);
+
+/* Gradient-ascent polish (Adam on box-normalised coordinates), best-so-far kept. */
+void or_polish(const or_line *L, const or_bounds *B, int64_t n, const int32_t *cmp,
+               const int32_t *t, const float *p_in, double lr, int32_t steps,
+               double *p_out, double *S_out);
+
+/* Per-trace scaled reduced-precision storage: scale = max|u| (1 if the trace
+ * is all zero), q = round-to-nearest-even(binary32(u / scale)). */
+void or_quantize(const float *u, int64_t n_tr, int32_t nt, int32_t dtype /*1 f16, 2 bf16*/,
+                 uint16_t *q, float *scale);
+double or_half_to_double(uint16_t h);
+double or_bf16_to_double(uint16_t h);
+
+/* Reference maximum of S per sample: uniform grid then local refinement. */
+void or_sref(const or_line *L, const or_bounds *B, int64_t n, const int32_t *cmp,
+             const int32_t *t, const int32_t *grid /*[3] points per axis*/, int32_t n_refine,
+             double *S_ref, double *p_ref);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,344 @@
+/*
+ * Differential evolution per domain and the evolution-by-neighbourhood-
+ * similarity (ENS) sweep.  Test infrastructure (see oracle.h).
+ *
+ * Per domain (ZO sample), section "JADE applied to traveltime parameter
+ * search": NP individuals drawn uniformly in the parameter box and scored
+ * (Initializing); the best individual located (Sorting, with P = 1 so the
+ * p-best is the best); for each individual i a mutant built from i, the best
+ * and two other random members (Mutation and crossover, current-to-best/1),
+ * crossed with i; all trials scored, then each trial replaces its parent when
+ * its semblance is at least as large, the old population being kept until
+ * every comparison is made (Selection).  After NG generations the best is
+ * returned.  Evaluations per domain: NP (1 + NG) (eq. jade_semblance).
+ *
+ * Fixed-F, fixed-CR reading: the paper takes JADE's parameter adaptation and
+ * archive from earlier work without stating them; this oracle uses constant
+ * F and CR, binomial crossover with one forced dimension, and midpoint repair
+ * of out-of-box mutant coordinates toward the parent.
+ *
+ * Random numbers: one Philox-4x64-10 block per (sample, stage, generation,
+ * slot), key (seed, 0).  Generation 0 words 0..2 give the initial coordinates
+ * (top 24 bits as a binary32 fraction); later generations: word 0 high/low
+ * halves draw r1 in [0,NP-1) and r2 in [0,NP-2) by multiply-shift, skipping
+ * the excluded indices in ascending order; word 1 high half draws the forced
+ * dimension; word 1 low, word 2 high, word 2 low are the crossover draws of
+ * dimensions 0, 1, 2, compared against ceil(CR 2^32).
+ *
+ * ENS (sections "Information propagation" and "Evolution by neighborhood
+ * similarity"), N_skip = 0: stage 0 sweeps each interactive domain (bucket of
+ * consecutive output CMPs) left to right with NP_f, NG_f; the best of
+ * (t, previous trace) replaces slot 0 of (t, trace).  Each of the N_cycle
+ * cycles then sweeps right to left and left to right with NP_bf, NG_bf; slots
+ * 0, 1, 2 take the bests of (t-1, trace), (t+1, trace) and (t, previous trace
+ * of this sweep), slot 3 the current best of (t, trace) with its stored
+ * score (not re-evaluated), the rest are random; a missing neighbour leaves
+ * its slot random.  All t of one trace step read the state as it was before
+ * the step (the t are processed concurrently).  Evaluations per sample:
+ * NP_f (1 + NG_f) + N_cycle 2 (NP_bf (1 + NG_bf) - 1) (eq. ens_semblance).
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "oracle.h"
+
+#define MAXNP 64
+
+int32_t or_pop_size(const or_de_cfg *cfg, int32_t nt, int32_t n0)
+{
+    if (nt <= 1)
+        return cfg->np_lo;
+    double v = cfg->np_lo + (double)(cfg->np_hi - cfg->np_lo) * (double)n0 / (double)(nt - 1);
+    return (int32_t)floor(v + 0.5);
+}
+
+void or_sample_bounds(const or_line *L, const or_bounds *B, int32_t n0, float lo[3], float hi[3])
+{
+    const float dt = (float)L->dt;
+    const float t0 = (float)n0 * dt;
+    const float den = t0 > dt ? t0 : dt;
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = B->lo[d];
+        hi[d] = B->hi[d];
+        if (B->inv_t0_mask >> d & 1u) {
+            lo[d] = lo[d] / den;
+            hi[d] = hi[d] / den;
+        }
+    }
+}
+
+static void rng_words(uint64_t seed, uint64_t sample, uint64_t stage, uint64_t gen, uint64_t slot,
+                      uint64_t w[4])
+{
+    const uint64_t ctr[4] = {sample, stage, gen, slot};
+    const uint64_t key[2] = {seed, 0};
+    or_philox4x64_10(ctr, key, w);
+}
+
+static void random_individual(const uint64_t w[4], int P, const float *lo, const float *hi,
+                              float *x)
+{
+    for (int d = 0; d < P; ++d) {
+        float u = (float)(w[d] >> 40) * 0x1p-24f;
+        float range = hi[d] - lo[d];
+        float step = u * range;
+        x[d] = lo[d] + step;
+    }
+}
+
+void or_de_trial(int32_t np, int32_t P, const float *pop, const double *S, const uint64_t *words,
+                 float F, float CR, const float *lo, const float *hi, float *trial)
+{
+    int32_t b = 0;
+    for (int32_t i = 1; i < np; ++i)
+        if (S[i] > S[b])
+            b = i;
+    const uint64_t thr = (uint64_t)ceil((double)CR * 4294967296.0);
+    for (int32_t i = 0; i < np; ++i) {
+        const uint64_t *w = words + 4 * i;
+        uint32_t r1 = (uint32_t)(((w[0] >> 32) * (uint64_t)(np - 1)) >> 32);
+        if (r1 >= (uint32_t)i)
+            r1 += 1;
+        uint32_t r2 = (uint32_t)(((w[0] & 0xffffffffULL) * (uint64_t)(np - 2)) >> 32);
+        uint32_t ex_lo = (uint32_t)i < r1 ? (uint32_t)i : r1;
+        uint32_t ex_hi = (uint32_t)i < r1 ? r1 : (uint32_t)i;
+        if (r2 >= ex_lo)
+            r2 += 1;
+        if (r2 >= ex_hi)
+            r2 += 1;
+        uint32_t jr = (uint32_t)(((w[1] >> 32) * (uint64_t)P) >> 32);
+        uint64_t cr[3] = {w[1] & 0xffffffffULL, w[2] >> 32, w[2] & 0xffffffffULL};
+        for (int d = 0; d < P; ++d) {
+            float xi = pop[i * P + d];
+            float t1 = pop[b * P + d] - xi;
+            float t2 = pop[r1 * P + d] - pop[r2 * P + d];
+            float m1 = F * t1;
+            float m2 = F * t2;
+            float v = xi + m1;
+            v = v + m2;
+            if (v < lo[d])
+                v = (lo[d] + xi) * 0.5f;
+            else if (v > hi[d])
+                v = (hi[d] + xi) * 0.5f;
+            int take = (cr[d] < thr) || ((uint32_t)d == jr);
+            trial[i * P + d] = take ? v : xi;
+        }
+    }
+}
+
+/* ---------------------------------------------------------------------------
+ * objective */
+
+typedef struct {
+    const or_line *L;
+    const or_de_cfg *cfg;
+    int P;
+} objective_ctx;
+
+static double objective(const objective_ctx *o, int32_t j, int32_t n0, const float *x,
+                        const float *lo, const float *hi)
+{
+    if (o->cfg->objective == 0) {
+        double p[3] = {0, 0, 0};
+        for (int d = 0; d < o->P; ++d)
+            p[d] = (double)x[d];
+        return or_semblance(o->L, j, n0, p, NULL, NULL);
+    }
+    /* mock objectives in box-normalised coordinates, optimum at c_d = 0.3 + 0.1 d */
+    double r2 = 0.0, inside = 1.0;
+    for (int d = 0; d < o->P; ++d) {
+        double z = ((double)x[d] - lo[d]) / ((double)hi[d] - lo[d]);
+        double c = 0.3 + 0.1 * d;
+        r2 += (z - c) * (z - c);
+        if (fabs(z - c) > 0.02)
+            inside = 0.0;
+    }
+    if (o->cfg->objective == 1)
+        return 1.0 / (1.0 + 50.0 * r2);
+    return inside;
+}
+
+/* NG generations of DE on one domain; pop/S hold the scored initial
+ * population on entry and the final one on exit.  Returns evaluations. */
+static int64_t evolve(const objective_ctx *o, uint64_t seed, uint64_t sample, uint64_t stage,
+                      int32_t j, int32_t n0, int np, int ng, const float *lo, const float *hi,
+                      float *pop, double *S)
+{
+    const int P = o->P;
+    float trial[MAXNP * 3];
+    double St[MAXNP];
+    uint64_t words[MAXNP * 4];
+    int64_t evals = 0;
+    for (int g = 1; g <= ng; ++g) {
+        for (int i = 0; i < np; ++i)
+            rng_words(seed, sample, stage, (uint64_t)g, (uint64_t)i, words + 4 * i);
+        or_de_trial(np, P, pop, S, words, o->cfg->F, o->cfg->CR, lo, hi, trial);
+        for (int i = 0; i < np; ++i) {
+            St[i] = objective(o, j, n0, trial + i * P, lo, hi);
+            ++evals;
+        }
+        for (int i = 0; i < np; ++i) {
+            if (St[i] >= S[i]) {
+                memcpy(pop + i * P, trial + i * P, sizeof(float) * (size_t)P);
+                S[i] = St[i];
+            }
+        }
+    }
+    return evals;
+}
+
+static int best_index(const double *S, int np)
+{
+    int b = 0;
+    for (int i = 1; i < np; ++i)
+        if (S[i] > S[b])
+            b = i;
+    return b;
+}
+
+static void clamp_into(float *x, int P, const float *lo, const float *hi)
+{
+    for (int d = 0; d < P; ++d) {
+        if (x[d] < lo[d])
+            x[d] = lo[d];
+        if (x[d] > hi[d])
+            x[d] = hi[d];
+    }
+}
+
+static int64_t plain_de(const objective_ctx *o, const or_bounds *B, uint64_t seed,
+                        const int32_t *cmp_out, int32_t n_out, int32_t t_begin, int32_t t_end,
+                        float *params_out, double *S_out)
+{
+    const or_line *L = o->L;
+    const int P = o->P;
+    const int32_t n_t = t_end - t_begin;
+    int64_t total = 0;
+#pragma omp parallel for collapse(2) schedule(dynamic, 4) reduction(+ : total)
+    for (int32_t oi = 0; oi < n_out; ++oi) {
+        for (int32_t tt = 0; tt < n_t; ++tt) {
+            const int32_t j = cmp_out[oi], n0 = t_begin + tt;
+            const uint64_t sample = (uint64_t)n0 + (uint64_t)L->nt * (uint64_t)j;
+            const int np = or_pop_size(o->cfg, L->nt, n0);
+            float lo[3], hi[3], pop[MAXNP * 3];
+            double S[MAXNP];
+            uint64_t w[4];
+            or_sample_bounds(L, B, n0, lo, hi);
+            for (int i = 0; i < np; ++i) {
+                rng_words(seed, sample, 0, 0, (uint64_t)i, w);
+                random_individual(w, P, lo, hi, pop + i * P);
+                S[i] = objective(o, j, n0, pop + i * P, lo, hi);
+            }
+            int64_t ev = np + evolve(o, seed, sample, 0, j, n0, np, o->cfg->ng_f, lo, hi, pop, S);
+            int b = best_index(S, np);
+            const int64_t idx = (int64_t)oi * n_t + tt;
+            for (int d = 0; d < P; ++d)
+                params_out[idx * P + d] = pop[b * P + d];
+            S_out[idx] = S[b];
+            total += ev;
+        }
+    }
+    return total;
+}
+
+static int64_t ens_sweep(const objective_ctx *o, const or_bounds *B, uint64_t seed,
+                         const int32_t *cmp_out, int32_t n_out, int32_t t_begin, int32_t t_end,
+                         float *params_out, double *S_out)
+{
+    const or_line *L = o->L;
+    const or_de_cfg *cfg = o->cfg;
+    const int P = o->P;
+    const int32_t n_t = t_end - t_begin;
+    const int64_t n_s = (int64_t)n_out * n_t;
+    float *X = calloc((size_t)(n_s * P), sizeof(float)), *Y = calloc((size_t)(n_s * P), sizeof(float));
+    double *XS = calloc((size_t)n_s, sizeof(double)), *YS = calloc((size_t)n_s, sizeof(double));
+    const int n_stage = 1 + 2 * cfg->n_cycle;
+    int64_t total = 0;
+
+    for (int stage = 0; stage < n_stage; ++stage) {
+        const int forward = (stage % 2) == 0;
+        for (int32_t b0 = 0; b0 < n_out; b0 += cfg->n_bucket) {
+            const int32_t nb = (n_out - b0) < cfg->n_bucket ? (n_out - b0) : cfg->n_bucket;
+            for (int32_t k = 0; k < nb; ++k) {
+                const int32_t pos = forward ? k : nb - 1 - k;
+                const int32_t oi = b0 + pos;
+                const int32_t prev = forward ? oi - 1 : oi + 1;
+                const int32_t j = cmp_out[oi];
+                int64_t step_total = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : step_total)
+                for (int32_t tt = 0; tt < n_t; ++tt) {
+                    const int32_t n0 = t_begin + tt;
+                    const uint64_t sample = (uint64_t)n0 + (uint64_t)L->nt * (uint64_t)j;
+                    const int np = stage == 0 ? or_pop_size(cfg, L->nt, n0) : cfg->np_bf;
+                    const int ng = stage == 0 ? cfg->ng_f : cfg->ng_bf;
+                    float lo[3], hi[3], pop[MAXNP * 3];
+                    double S[MAXNP];
+                    int scored[MAXNP];
+                    uint64_t w[4];
+                    or_sample_bounds(L, B, n0, lo, hi);
+                    for (int i = 0; i < np; ++i) {
+                        rng_words(seed, sample, (uint64_t)stage, 0, (uint64_t)i, w);
+                        random_individual(w, P, lo, hi, pop + i * P);
+                        scored[i] = 0;
+                    }
+                    const int64_t here = (int64_t)oi * n_t + tt;
+                    if (stage == 0) {
+                        if (cfg->inject && k > 0) {
+                            const int64_t src = (int64_t)prev * n_t + tt;
+                            memcpy(pop, Y + src * P, sizeof(float) * (size_t)P);
+                            clamp_into(pop, P, lo, hi);
+                        }
+                    } else {
+                        if (cfg->inject && tt > 0) {
+                            memcpy(pop + 0 * P, X + (here - 1) * P, sizeof(float) * (size_t)P);
+                            clamp_into(pop + 0 * P, P, lo, hi);
+                        }
+                        if (cfg->inject && tt < n_t - 1) {
+                            memcpy(pop + 1 * P, X + (here + 1) * P, sizeof(float) * (size_t)P);
+                            clamp_into(pop + 1 * P, P, lo, hi);
+                        }
+                        if (cfg->inject && k > 0) {
+                            const int64_t src = (int64_t)prev * n_t + tt;
+                            memcpy(pop + 2 * P, Y + src * P, sizeof(float) * (size_t)P);
+                            clamp_into(pop + 2 * P, P, lo, hi);
+                        }
+                        /* the domain's own best so far, with its stored score */
+                        memcpy(pop + 3 * P, X + here * P, sizeof(float) * (size_t)P);
+                        S[3] = XS[here];
+                        scored[3] = 1;
+                    }
+                    int64_t ev = 0;
+                    for (int i = 0; i < np; ++i) {
+                        if (!scored[i]) {
+                            S[i] = objective(o, j, n0, pop + i * P, lo, hi);
+                            ++ev;
+                        }
+                    }
+                    ev += evolve(o, seed, sample, (uint64_t)stage, j, n0, np, ng, lo, hi, pop, S);
+                    int bi = best_index(S, np);
+                    memcpy(Y + here * P, pop + bi * P, sizeof(float) * (size_t)P);
+                    YS[here] = S[bi];
+                    step_total += ev;
+                }
+                total += step_total;
+            }
+        }
+        float *tp = X; X = Y; Y = tp;
+        double *ts = XS; XS = YS; YS = ts;
+    }
+    memcpy(params_out, X, sizeof(float) * (size_t)(n_s * P));
+    memcpy(S_out, XS, sizeof(double) * (size_t)n_s);
+    free(X); free(Y); free(XS); free(YS);
+    return total;
+}
+
+int64_t or_search(const or_line *L, const or_bounds *B, const or_de_cfg *cfg, uint64_t seed,
+                  const int32_t *cmp_out, int32_t n_out, int32_t t_begin, int32_t t_end,
+                  float *params_out, double *S_out)
+{
+    objective_ctx o = {L, cfg, L->op};
+    if (!cfg->ens_enabled)
+        return plain_de(&o, B, seed, cmp_out, n_out, t_begin, t_end, params_out, S_out);
+    return ens_sweep(&o, B, seed, cmp_out, n_out, t_begin, t_end, params_out, S_out);
+}
