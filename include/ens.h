@@ -1,0 +1,245 @@
+/*
+ * libens — windowed-semblance traveltime-parameter search with evolution by
+ * neighbourhood similarity (ENS), for AMD Instinct MI355X (gfx950).
+ *
+ * Method: arXiv 2304.11399.  For every zero-offset output sample (t, tr) the
+ * library searches the traveltime-operator parameters that maximise the
+ * semblance of the data along the operator (section "Traveltime parameter
+ * search", eqs. f, S, Sf); each sample runs a differential evolution
+ * (section "JADE applied to traveltime parameter search") and, with ENS
+ * enabled, best individuals are exchanged between neighbouring samples in a
+ * forward exploration sweep followed by backward/forward exploitation sweeps
+ * over the traces of each interactive domain (sections "Information
+ * propagation" and "Evolution by neighborhood similarity").
+ *
+ * Operators (h = full source-receiver offset, dm = midpoint displacement of
+ * a trace's CMP from the output CMP, t0 = n0 dt):
+ *     ENS_OP_CMP (1 parameter C):          t^2 = t0^2 + C h^2
+ *     ENS_OP_CRS (3 parameters A, B, C):   t^2 = (t0 + A dm)^2 + B t0 dm^2 + C t0 h^2
+ *
+ * Semblance of M participating traces (t^2 >= 0 and 0 <= t/dt <= nt-1) over
+ * the window k = -w..w around each trace's traveltime tau = t/dt = n + f:
+ *     a_ik = (1-f) u_i[n+k] + f u_i[n+k+1]   (samples outside the trace read 0)
+ *     S = sum_k (sum_i a_ik)^2 / (M sum_k sum_i a_ik^2),  S = 0 if M = 0 or the
+ *     energy is 0.
+ *
+ * Conventions for every call:
+ *  - Pointers are DEVICE pointers unless marked "host".  The caller owns
+ *    every buffer it passes; the library never frees them and keeps no
+ *    pointer to them after the call returns, except that ens_bind copies the
+ *    traces into its own store.
+ *  - Work is ordered on the context's stream.  Device outputs are valid once
+ *    that stream has been synchronised; host outputs (counters) are written
+ *    before the call returns (those calls synchronise the stream once).
+ *  - Arguments are validated on the host before anything is launched; on an
+ *    error nothing is written to any output, the call returns a negative
+ *    ens_status and ens_last_error(ctx) describes the problem.  No C++
+ *    exception crosses this interface.  A context is used by one host thread
+ *    at a time.
+ *  - Every struct begins with struct_size = sizeof(struct); a smaller value
+ *    is rejected with ENS_E_INVALID.
+ */
+#ifndef ENS_H
+#define ENS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ENS_OK = 0,
+    ENS_E_INVALID = -1,     /* null pointer, bad dtype/op, inconsistent sizes, struct_size */
+    ENS_E_RANGE = -2,       /* even or too large window, NP < 4 or > 64, NP_bf < 5, lo >= hi,
+                               n_skip != 0, index out of range */
+    ENS_E_HIP = -3,         /* a HIP runtime call failed (message has the HIP error string) */
+    ENS_E_OOM = -4,         /* device allocation failed */
+    ENS_E_UNSUPPORTED = -5, /* valid request this build does not implement */
+    ENS_E_STATE = -6        /* call needs ens_bind first */
+} ens_status;
+
+enum { ENS_DTYPE_F32 = 0, ENS_DTYPE_F16 = 1, ENS_DTYPE_BF16 = 2 };
+enum { ENS_OP_CMP = 1, ENS_OP_CRS = 3 };
+enum { ENS_MAX_HALF_WINDOW = 7 };       /* window W = 2w+1 <= 15 */
+enum { ENS_MAX_POP = 64 };
+
+typedef struct ens_ctx ens_ctx;
+
+/* Trace samples, read once by ens_bind.  data: device, [n_traces][ld] binary32,
+ * sample n of trace i at data[i*ld + n], time n*dt.  store_dtype chooses the
+ * library's own storage: ENS_DTYPE_F32 keeps binary32; F16/BF16 keep
+ * q_i[n] = round-to-nearest-even(binary32(u_i[n] / s_i)) with the per-trace
+ * scale s_i = max_n |u_i[n]| (1 for an all-zero trace), plus a binary32 copy
+ * for the binary64 re-scoring. */
+typedef struct {
+    uint32_t struct_size;
+    const float *data;
+    int64_t n_traces;
+    int32_t nt;
+    int64_t ld;
+    float dt;
+    int32_t store_dtype;
+} ens_traces;
+
+/* Acquisition geometry, host arrays.  Traces sorted by (CMP, offset);
+ * cmp_ptr[c] .. cmp_ptr[c+1]-1 are the traces of CMP c, cmp_ptr[0] = 0,
+ * cmp_ptr[n_cmp] = n_traces, non-decreasing.  offset: full offset (m) per
+ * trace.  dx: CMP spacing (m); dm = (c - j) dx. */
+typedef struct {
+    uint32_t struct_size;
+    const int64_t *cmp_ptr;  /* host [n_cmp+1] */
+    int32_t n_cmp;
+    float dx;
+    const float *offset;     /* host [n_traces] */
+} ens_geometry;
+
+/* Semblance configuration (#config of eq. Sf): operator, window length and
+ * midpoint half-aperture in CMPs, ap_lo at time index 0 and ap_hi at nt-1,
+ * a(n0) = floor(ap_lo + (ap_hi - ap_lo) n0 / (nt-1) + 1/2). */
+typedef struct {
+    uint32_t struct_size;
+    int32_t op;
+    int32_t window;          /* odd, <= 2*ENS_MAX_HALF_WINDOW+1 */
+    int32_t ap_lo, ap_hi;
+} ens_sem_cfg;
+
+/* Output grid: output CMPs (host list; NULL = all CMPs in order) and time
+ * indices [t_begin, t_end).  ZO sample id = t + nt*cmp.  Results are laid out
+ * [n_cmp_out][t_end - t_begin] with t fastest. */
+typedef struct {
+    uint32_t struct_size;
+    const int32_t *cmp_out;  /* host [n_cmp_out] or NULL */
+    int32_t n_cmp_out;
+    int32_t t_begin, t_end;
+} ens_t0_grid;
+
+/* Parameter box.  Bit d of inv_t0_mask set: bounds d are given for p_d t0 and
+ * are divided per sample by max(t0, dt) (binary32: lo_d / max(n0*dt, dt)). */
+typedef struct {
+    uint32_t struct_size;
+    float lo[3], hi[3];
+    uint32_t inv_t0_mask;
+} ens_bounds;
+
+/* Search configuration.  NP_f(n0) = floor(np_lo + (np_hi-np_lo) n0/(nt-1) + 1/2).
+ * ens_enabled = 0: every sample evolves on its own (NP_f, NG_f) — the
+ * per-domain search the paper compares against.  ens_enabled = 1: ENS with
+ * buckets of n_bucket consecutive output CMPs, stage 0 (NP_f, NG_f) and
+ * n_cycle backward/forward cycles (NP_bf, NG_bf); inject = 0 disables every
+ * exchange between samples.  n_skip must be 0.  F, CR: fixed mutation factor
+ * and crossover rate.  polish_steps > 0: that many Adam steps of learning
+ * rate polish_lr on box-normalised coordinates per winner, keeping the best
+ * point.  rescore_fp64: also write the binary64 semblance of each winner,
+ * computed from the binary32 copy of the traces. */
+typedef struct {
+    uint32_t struct_size;
+    int32_t np_lo, np_hi;
+    int32_t ng_f;
+    int32_t np_bf, ng_bf;
+    int32_t n_cycle;
+    int32_t n_skip;
+    int32_t n_bucket;
+    int32_t ens_enabled;
+    int32_t inject;
+    float F, CR;
+    int32_t polish_steps;
+    float polish_lr;
+    int32_t rescore_fp64;
+} ens_de_cfg;
+
+/* Search outputs (device, [n_cmp_out][n_t][P] and [n_cmp_out][n_t]); S64 and
+ * S_pre_polish may be NULL.  n_evals, sum_m (host) receive the evaluation
+ * count and the total of participating traces over all evaluations. */
+typedef struct {
+    uint32_t struct_size;
+    float *params;
+    float *S;
+    double *S64;
+    float *S_pre_polish;
+    int64_t n_evals;
+    int64_t sum_m;
+} ens_result;
+
+/* A batch of candidates: output CMP, time index and parameters [n][P]
+ * (device).  Throughput is best when consecutive candidates share a CMP. */
+typedef struct {
+    uint32_t struct_size;
+    int64_t n;
+    const int32_t *cmp;
+    const int32_t *t;
+    const float *params;
+} ens_candidates;
+
+/* Search-kernel launch shape; zero fields mean "let the library choose". */
+typedef struct {
+    uint32_t struct_size;
+    int32_t waves_per_sample_group;  /* trace slices per population (1, 2, 4, 8) */
+    int32_t use_graph;               /* 1: replay the trace-step launches as a HIP graph */
+} ens_tuning;
+
+/* ---- context ----------------------------------------------------------- */
+
+/* Create a context on the current HIP device ordering its work on `stream`
+ * (a hipStream_t; NULL = the null stream). */
+ens_status ens_ctx_create(ens_ctx **out, void *stream);
+void ens_ctx_destroy(ens_ctx *ctx);
+/* Message of the last failing call on ctx (empty string if none). */
+const char *ens_last_error(const ens_ctx *ctx);
+/* Library version string. */
+const char *ens_version(void);
+ens_status ens_set_tuning(ens_ctx *ctx, const ens_tuning *tuning);
+
+/* ---- data --------------------------------------------------------------- */
+
+/* Bind #data and #config (eq. Sf): copies the traces into the library's
+ * padded store (quantising them if asked) and uploads the geometry. */
+ens_status ens_bind(ens_ctx *ctx, const ens_traces *traces, const ens_geometry *geometry,
+                    const ens_sem_cfg *sem);
+
+/* Per-trace scaled quantisation of [n_traces][ld] binary32 samples into
+ * q: device [n_traces][nt] uint16 (binary16 or bfloat16 bits) and scale:
+ * device [n_traces] (the same rule ens_bind applies). */
+ens_status ens_quantize(ens_ctx *ctx, const float *data, int64_t n_traces, int32_t nt, int64_t ld,
+                        int32_t dtype, uint16_t *q, float *scale);
+
+/* ---- the search --------------------------------------------------------- */
+
+/* Search every sample of t0_grid (section "Traveltime parameter search":
+ * maximise f(p) = S(p; #data, #config) within the box per sample). */
+ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *t0_grid, const ens_bounds *bounds,
+                      const ens_de_cfg *de_cfg, uint64_t seed, ens_result *out);
+
+/* ---- the objective and its adjoint --------------------------------------- */
+
+/* f(p) for a batch: S_out[n] (device); M_out[n] (device, may be NULL)
+ * receives the participating-trace counts.  Uses the bound store. */
+ens_status semblance_eval(ens_ctx *ctx, const ens_candidates *cands, float *S_out, int32_t *M_out);
+
+/* Binary64 semblance from the binary32 copy of the traces: S_out[n] (device). */
+ens_status semblance_eval64(ens_ctx *ctx, const ens_candidates *cands, double *S_out);
+
+/* dparams_out[n][P] = dS[n] * dS/dp through the interpolated gather, with M
+ * held fixed and the right derivative at integer traveltimes (device). */
+ens_status semblance_backward(ens_ctx *ctx, const ens_candidates *cands, const float *dS,
+                              float *dparams_out);
+
+/* ---- checks of the device building blocks -------------------------------- */
+
+/* Philox-4x64-10 blocks (Salmon et al., SC'11) for n counters (device
+ * [n][4] uint64) under key (device [2]): out device [n][4]. */
+ens_status ens_philox(ens_ctx *ctx, int64_t n, const uint64_t *counters, const uint64_t *key,
+                      uint64_t *out);
+
+/* One generation's trial vectors of the evolution for n_pop independent
+ * populations of size np (device pop [n_pop*np][P], S [n_pop*np], words
+ * [n_pop*np][4] generator outputs, lo/hi [n_pop][P]): trial out
+ * [n_pop*np][P].  The search kernels use the same device routine. */
+ens_status ens_de_trial(ens_ctx *ctx, int32_t n_pop, int32_t np, int32_t P, const float *pop,
+                        const float *S, const uint64_t *words, float F, float CR,
+                        const float *lo, const float *hi, float *trial);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,540 @@
+// C-ABI of libens: argument validation, the trace store, the search schedule
+// (plain per-sample evolution or ENS sweeps) and the objective entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ens.h"
+#include "device.h"
+#include "launch.h"
+
+namespace {
+
+using ens::PAD;
+using ens::TraceMeta;
+
+// Grow-only device buffer owned by a context.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    hipError_t ensure(size_t n)
+    {
+        if (n <= bytes) return hipSuccess;
+        if (p) {
+            hipError_t e = hipFree(p);
+            p = nullptr;
+            bytes = 0;
+            if (e != hipSuccess) return e;
+        }
+        if (n == 0) return hipSuccess;
+        hipError_t e = hipMalloc(&p, n);
+        if (e == hipSuccess) bytes = n;
+        return e;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <typename T> T *as() const { return static_cast<T *>(p); }
+};
+
+}  // namespace
+
+struct ens_ctx {
+    hipStream_t stream = nullptr;
+    std::string err;
+    ens_tuning tuning{};
+    // bound data (#data, #config)
+    bool bound = false;
+    int64_t n_tr = 0, ld = 0;
+    int32_t nt = 0, n_cmp = 0, store_dtype = ENS_DTYPE_F32;
+    float dt = 0.f, dx = 0.f;
+    int32_t op = 0, window = 0, ap_lo = 0, ap_hi = 0;
+    DevBuf store, master, scale, meta, cmp_ptr, ap_tab;
+    // search workspace
+    DevBuf lo_tab, hi_tab, items, X, XS, Y, YS, counters, cmp_out, flag;
+    ~ens_ctx()
+    {
+        for (DevBuf *b : {&store, &master, &scale, &meta, &cmp_ptr, &ap_tab, &lo_tab, &hi_tab, &items,
+                          &X, &XS, &Y, &YS, &counters, &cmp_out, &flag})
+            b->release();
+    }
+};
+
+namespace {
+
+ens_status fail(ens_ctx *ctx, ens_status st, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+ens_status fail(ens_ctx *ctx, ens_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    return st;
+}
+
+#define HIP_OR_FAIL(ctx, expr)                                                                    \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return fail(ctx, e_ == hipErrorOutOfMemory ? ENS_E_OOM : ENS_E_HIP, "%s: %s", #expr, \
+                        hipGetErrorString(e_));                                                   \
+    } while (0)
+
+int32_t lerp_round(int32_t lo, int32_t hi, int32_t n0, int32_t nt)
+{
+    if (nt <= 1) return lo;
+    const double v = lo + static_cast<double>(hi - lo) * static_cast<double>(n0) / static_cast<double>(nt - 1);
+    return static_cast<int32_t>(std::floor(v + 0.5));
+}
+
+// Per-sample box: bounds whose mask bit is set are divided by max(n0 dt, dt)
+// in binary32.
+void sample_box(const ens_bounds &b, int32_t n0, float dt, float lo[3], float hi[3])
+{
+    const float t0 = static_cast<float>(n0) * dt;
+    const float den = t0 > dt ? t0 : dt;
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = b.lo[d];
+        hi[d] = b.hi[d];
+        if (b.inv_t0_mask >> d & 1u) {
+            lo[d] = lo[d] / den;
+            hi[d] = hi[d] / den;
+        }
+    }
+}
+
+ens::StoreView view_of(const ens_ctx *c, bool master)
+{
+    ens::StoreView v{};
+    const bool use_master = master && c->store_dtype != ENS_DTYPE_F32;
+    v.store = use_master ? c->master.p : c->store.p;
+    v.ld = c->ld;
+    v.scale = (c->store_dtype == ENS_DTYPE_F32 || use_master) ? nullptr : c->scale.as<float>();
+    v.meta = c->meta.as<TraceMeta>();
+    v.cmp_ptr = c->cmp_ptr.as<int64_t>();
+    v.n_cmp = c->n_cmp;
+    v.nt = c->nt;
+    v.dt = c->dt;
+    v.dx = c->dx;
+    v.ap_tab = c->ap_tab.as<int32_t>();
+    return v;
+}
+
+bool finite(float x) { return std::isfinite(x); }
+
+// Device-side range check of candidate indices (they live in device memory).
+ens_status check_candidates(ens_ctx *ctx, const ens_candidates *cands);
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char *ens_version(void) { return "libens 0.1 (gfx950)"; }
+
+ens_status ens_ctx_create(ens_ctx **out, void *stream)
+{
+    if (!out) return ENS_E_INVALID;
+    *out = nullptr;
+    ens_ctx *c = new (std::nothrow) ens_ctx();
+    if (!c) return ENS_E_OOM;
+    c->stream = static_cast<hipStream_t>(stream);
+    c->tuning.struct_size = sizeof(ens_tuning);
+    *out = c;
+    return ENS_OK;
+}
+
+void ens_ctx_destroy(ens_ctx *ctx) { delete ctx; }
+
+const char *ens_last_error(const ens_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+ens_status ens_set_tuning(ens_ctx *ctx, const ens_tuning *t)
+{
+    if (!ctx) return ENS_E_INVALID;
+    if (!t || t->struct_size < sizeof(ens_tuning)) return fail(ctx, ENS_E_INVALID, "ens_tuning: bad struct_size");
+    const int w = t->waves_per_sample_group;
+    if (!(w == 0 || w == 1 || w == 2 || w == 4 || w == 8))
+        return fail(ctx, ENS_E_RANGE, "waves_per_sample_group must be 0, 1, 2, 4 or 8 (got %d)", w);
+    ctx->tuning = *t;
+    ctx->err.clear();
+    return ENS_OK;
+}
+
+ens_status ens_bind(ens_ctx *ctx, const ens_traces *tr, const ens_geometry *g, const ens_sem_cfg *sem)
+{
+    if (!ctx) return ENS_E_INVALID;
+    if (!tr || !g || !sem) return fail(ctx, ENS_E_INVALID, "ens_bind: null argument");
+    if (tr->struct_size < sizeof(ens_traces) || g->struct_size < sizeof(ens_geometry) ||
+        sem->struct_size < sizeof(ens_sem_cfg))
+        return fail(ctx, ENS_E_INVALID, "ens_bind: struct_size too small");
+    if (!tr->data || !g->cmp_ptr || !g->offset) return fail(ctx, ENS_E_INVALID, "ens_bind: null array");
+    if (tr->n_traces < 1 || tr->nt < 2 || tr->ld < tr->nt)
+        return fail(ctx, ENS_E_INVALID, "ens_bind: need n_traces >= 1, nt >= 2, ld >= nt");
+    if (tr->nt > (1 << 20)) return fail(ctx, ENS_E_RANGE, "ens_bind: nt too large");
+    if (!(tr->dt > 0.f) || !finite(tr->dt) || !(g->dx > 0.f) || !finite(g->dx))
+        return fail(ctx, ENS_E_RANGE, "ens_bind: dt and dx must be positive");
+    if (tr->store_dtype < ENS_DTYPE_F32 || tr->store_dtype > ENS_DTYPE_BF16)
+        return fail(ctx, ENS_E_INVALID, "ens_bind: unknown store dtype %d", tr->store_dtype);
+    if (g->n_cmp < 1) return fail(ctx, ENS_E_INVALID, "ens_bind: n_cmp < 1");
+    if (g->cmp_ptr[0] != 0 || g->cmp_ptr[g->n_cmp] != tr->n_traces)
+        return fail(ctx, ENS_E_INVALID, "ens_bind: cmp_ptr must start at 0 and end at n_traces");
+    for (int32_t c = 0; c < g->n_cmp; ++c)
+        if (g->cmp_ptr[c + 1] < g->cmp_ptr[c]) return fail(ctx, ENS_E_INVALID, "ens_bind: cmp_ptr decreases at %d", c);
+    for (int64_t i = 0; i < tr->n_traces; ++i)
+        if (!finite(g->offset[i])) return fail(ctx, ENS_E_INVALID, "ens_bind: offset[%lld] not finite", (long long)i);
+    if (sem->op != ENS_OP_CMP && sem->op != ENS_OP_CRS) return fail(ctx, ENS_E_INVALID, "ens_bind: unknown op %d", sem->op);
+    if (sem->window < 1 || sem->window % 2 == 0 || !ens::window_supported(sem->window))
+        return fail(ctx, ENS_E_RANGE, "ens_bind: window must be odd, 3..%d (got %d)", 2 * ENS_MAX_HALF_WINDOW + 1,
+                    sem->window);
+    if (sem->ap_lo < 0 || sem->ap_hi < 0) return fail(ctx, ENS_E_RANGE, "ens_bind: negative aperture");
+
+    const int64_t n_tr = tr->n_traces;
+    const int32_t nt = tr->nt;
+    const int64_t ld = ((nt + 2 * PAD) + 63) / 64 * 64;
+    ctx->bound = false;
+    const size_t elem = tr->store_dtype == ENS_DTYPE_F32 ? 4 : 2;
+    HIP_OR_FAIL(ctx, ctx->store.ensure(static_cast<size_t>(n_tr) * ld * elem));
+    HIP_OR_FAIL(ctx, ctx->scale.ensure(static_cast<size_t>(n_tr) * sizeof(float)));
+    if (tr->store_dtype == ENS_DTYPE_F32) {
+        HIP_OR_FAIL(ctx, ens::launch_store_f32(tr->data, tr->ld, n_tr, nt, ld, ctx->store.as<float>(), ctx->stream));
+    } else {
+        HIP_OR_FAIL(ctx, ctx->master.ensure(static_cast<size_t>(n_tr) * ld * 4));
+        HIP_OR_FAIL(ctx, ens::launch_store_f32(tr->data, tr->ld, n_tr, nt, ld, ctx->master.as<float>(), ctx->stream));
+        HIP_OR_FAIL(ctx, ens::launch_quantize(tr->data, tr->ld, n_tr, nt, tr->store_dtype, ctx->store.as<uint16_t>(),
+                                              ld, PAD, ctx->scale.as<float>(), ctx->stream));
+    }
+    std::vector<TraceMeta> meta(static_cast<size_t>(n_tr));
+    for (int32_t c = 0; c < g->n_cmp; ++c)
+        for (int64_t i = g->cmp_ptr[c]; i < g->cmp_ptr[c + 1]; ++i) {
+            const float h = g->offset[i];
+            meta[i].cx = static_cast<float>(c) * g->dx;
+            meta[i].h2 = h * h;
+            meta[i].cmp = c;
+            meta[i].h = h;
+        }
+    std::vector<int32_t> ap(static_cast<size_t>(nt));
+    for (int32_t n0 = 0; n0 < nt; ++n0) ap[n0] = lerp_round(sem->ap_lo, sem->ap_hi, n0, nt);
+    HIP_OR_FAIL(ctx, ctx->meta.ensure(meta.size() * sizeof(TraceMeta)));
+    HIP_OR_FAIL(ctx, ctx->cmp_ptr.ensure(sizeof(int64_t) * (g->n_cmp + 1)));
+    HIP_OR_FAIL(ctx, ctx->ap_tab.ensure(sizeof(int32_t) * nt));
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->meta.p, meta.data(), meta.size() * sizeof(TraceMeta),
+                                    hipMemcpyHostToDevice, ctx->stream));
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->cmp_ptr.p, g->cmp_ptr, sizeof(int64_t) * (g->n_cmp + 1),
+                                    hipMemcpyHostToDevice, ctx->stream));
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->ap_tab.p, ap.data(), sizeof(int32_t) * nt, hipMemcpyHostToDevice,
+                                    ctx->stream));
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->n_tr = n_tr;
+    ctx->ld = ld;
+    ctx->nt = nt;
+    ctx->n_cmp = g->n_cmp;
+    ctx->store_dtype = tr->store_dtype;
+    ctx->dt = tr->dt;
+    ctx->dx = g->dx;
+    ctx->op = sem->op;
+    ctx->window = sem->window;
+    ctx->ap_lo = sem->ap_lo;
+    ctx->ap_hi = sem->ap_hi;
+    ctx->bound = true;
+    ctx->err.clear();
+    return ENS_OK;
+}
+
+ens_status ens_quantize(ens_ctx *ctx, const float *data, int64_t n_traces, int32_t nt, int64_t ld,
+                        int32_t dtype, uint16_t *q, float *scale)
+{
+    if (!ctx) return ENS_E_INVALID;
+    if (!data || !q || !scale) return fail(ctx, ENS_E_INVALID, "ens_quantize: null pointer");
+    if (n_traces < 0 || nt < 1 || ld < nt) return fail(ctx, ENS_E_INVALID, "ens_quantize: bad sizes");
+    if (dtype != ENS_DTYPE_F16 && dtype != ENS_DTYPE_BF16)
+        return fail(ctx, ENS_E_INVALID, "ens_quantize: dtype must be F16 or BF16");
+    HIP_OR_FAIL(ctx, ens::launch_quantize(data, ld, n_traces, nt, dtype, q, nt, 0, scale, ctx->stream));
+    ctx->err.clear();
+    return ENS_OK;
+}
+
+ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *bounds,
+                      const ens_de_cfg *de, uint64_t seed, ens_result *out)
+{
+    if (!ctx) return ENS_E_INVALID;
+    if (!ctx->bound) return fail(ctx, ENS_E_STATE, "ens_search: call ens_bind first");
+    if (!grid || !bounds || !de || !out) return fail(ctx, ENS_E_INVALID, "ens_search: null argument");
+    if (grid->struct_size < sizeof(ens_t0_grid) || bounds->struct_size < sizeof(ens_bounds) ||
+        de->struct_size < sizeof(ens_de_cfg) || out->struct_size < sizeof(ens_result))
+        return fail(ctx, ENS_E_INVALID, "ens_search: struct_size too small");
+    if (!out->params || !out->S) return fail(ctx, ENS_E_INVALID, "ens_search: null output");
+    const int32_t P = ctx->op, nt = ctx->nt;
+    const int32_t n_out = grid->cmp_out ? grid->n_cmp_out : ctx->n_cmp;
+    if (n_out < 1) return fail(ctx, ENS_E_INVALID, "ens_search: no output CMPs");
+    if (grid->cmp_out)
+        for (int32_t o = 0; o < n_out; ++o)
+            if (grid->cmp_out[o] < 0 || grid->cmp_out[o] >= ctx->n_cmp)
+                return fail(ctx, ENS_E_RANGE, "ens_search: cmp_out[%d] = %d out of range", o, grid->cmp_out[o]);
+    if (grid->t_begin < 0 || grid->t_end > nt || grid->t_begin >= grid->t_end)
+        return fail(ctx, ENS_E_RANGE, "ens_search: need 0 <= t_begin < t_end <= nt");
+    for (int d = 0; d < P; ++d)
+        if (!finite(bounds->lo[d]) || !finite(bounds->hi[d]) || !(bounds->lo[d] < bounds->hi[d]))
+            return fail(ctx, ENS_E_RANGE, "ens_search: bounds %d need lo < hi", d);
+    if (de->n_skip != 0) return fail(ctx, ENS_E_RANGE, "ens_search: n_skip must be 0");
+    if (de->ng_f < 0 || de->ng_bf < 0 || de->n_cycle < 0)
+        return fail(ctx, ENS_E_RANGE, "ens_search: negative generation or cycle count");
+    if (de->np_lo < 4 || de->np_hi < 4 || de->np_lo > ENS_MAX_POP || de->np_hi > ENS_MAX_POP)
+        return fail(ctx, ENS_E_RANGE, "ens_search: NP_f must lie in [4, %d]", ENS_MAX_POP);
+    if (de->ens_enabled) {
+        if (de->n_bucket < 1) return fail(ctx, ENS_E_RANGE, "ens_search: n_bucket < 1");
+        if (de->n_cycle > 0 && (de->np_bf < 5 || de->np_bf > ENS_MAX_POP))
+            return fail(ctx, ENS_E_RANGE, "ens_search: NP_bf must lie in [5, %d]", ENS_MAX_POP);
+    }
+    if (!finite(de->F) || !finite(de->CR) || de->CR < 0.f || de->CR > 1.f)
+        return fail(ctx, ENS_E_RANGE, "ens_search: F must be finite and CR in [0, 1]");
+    if (de->polish_steps < 0 || (de->polish_steps > 0 && !(de->polish_lr > 0.f)))
+        return fail(ctx, ENS_E_RANGE, "ens_search: polish needs steps >= 0 and lr > 0");
+
+    const int32_t t_begin = grid->t_begin, n_t = grid->t_end - grid->t_begin;
+    const int64_t n_s = static_cast<int64_t>(n_out) * n_t;
+    hipStream_t st = ctx->stream;
+
+    // per-time tables
+    std::vector<float> lo(static_cast<size_t>(nt) * 3), hi(static_cast<size_t>(nt) * 3);
+    for (int32_t n0 = 0; n0 < nt; ++n0) sample_box(*bounds, n0, ctx->dt, &lo[n0 * 3], &hi[n0 * 3]);
+    std::vector<int32_t> cmp_out(static_cast<size_t>(n_out));
+    for (int32_t o = 0; o < n_out; ++o) cmp_out[o] = grid->cmp_out ? grid->cmp_out[o] : o;
+
+    // work items: consecutive t with equal NP packed floor(64/NP) per wave
+    auto build_items = [&](int32_t n_groups, bool per_stage0, std::vector<int4> &items) {
+        for (int32_t gidx = 0; gidx < n_groups; ++gidx) {
+            int32_t t = t_begin;
+            while (t < grid->t_end) {
+                const int32_t np = per_stage0 ? lerp_round(de->np_lo, de->np_hi, t, nt) : de->np_bf;
+                const int32_t per = ens::WAVE / np;
+                int32_t ns = 1;
+                while (ns < per && t + ns < grid->t_end &&
+                       (per_stage0 ? lerp_round(de->np_lo, de->np_hi, t + ns, nt) : de->np_bf) == np)
+                    ++ns;
+                items.push_back(make_int4(gidx, t, ns, np));
+                t += ns;
+            }
+        }
+    };
+    const bool ens = de->ens_enabled != 0;
+    const int32_t n_buckets = ens ? (n_out + de->n_bucket - 1) / de->n_bucket : 0;
+    std::vector<int4> items0, items_bf;
+    build_items(ens ? n_buckets : n_out, true, items0);
+    if (ens && de->n_cycle > 0) build_items(n_buckets, false, items_bf);
+
+    const size_t pbytes = sizeof(float) * static_cast<size_t>(n_s) * P, sbytes = sizeof(float) * n_s;
+    HIP_OR_FAIL(ctx, ctx->lo_tab.ensure(lo.size() * sizeof(float)));
+    HIP_OR_FAIL(ctx, ctx->hi_tab.ensure(hi.size() * sizeof(float)));
+    HIP_OR_FAIL(ctx, ctx->cmp_out.ensure(cmp_out.size() * sizeof(int32_t)));
+    HIP_OR_FAIL(ctx, ctx->items.ensure((items0.size() + items_bf.size()) * sizeof(int4)));
+    HIP_OR_FAIL(ctx, ctx->counters.ensure(4 * sizeof(unsigned long long)));
+    if (ens) {
+        HIP_OR_FAIL(ctx, ctx->X.ensure(pbytes));
+        HIP_OR_FAIL(ctx, ctx->Y.ensure(pbytes));
+        HIP_OR_FAIL(ctx, ctx->XS.ensure(sbytes));
+        HIP_OR_FAIL(ctx, ctx->YS.ensure(sbytes));
+    }
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->lo_tab.p, lo.data(), lo.size() * sizeof(float), hipMemcpyHostToDevice, st));
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->hi_tab.p, hi.data(), hi.size() * sizeof(float), hipMemcpyHostToDevice, st));
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->cmp_out.p, cmp_out.data(), cmp_out.size() * sizeof(int32_t),
+                                    hipMemcpyHostToDevice, st));
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->items.p, items0.data(), items0.size() * sizeof(int4),
+                                    hipMemcpyHostToDevice, st));
+    if (!items_bf.empty())
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->items.as<int4>() + items0.size(), items_bf.data(),
+                                        items_bf.size() * sizeof(int4), hipMemcpyHostToDevice, st));
+    HIP_OR_FAIL(ctx, hipMemsetAsync(ctx->counters.p, 0, 4 * sizeof(unsigned long long), st));
+
+    ens::SearchArgs a{};
+    a.sv = view_of(ctx, false);
+    a.cmp_out = ctx->cmp_out.as<int32_t>();
+    a.n_out = n_out;
+    a.t_begin = t_begin;
+    a.n_t = n_t;
+    a.lo_tab = ctx->lo_tab.as<float>();
+    a.hi_tab = ctx->hi_tab.as<float>();
+    a.n_bucket = de->n_bucket;
+    a.inject = de->inject;
+    a.nsl = ctx->tuning.waves_per_sample_group > 0 ? ctx->tuning.waves_per_sample_group : 4;
+    a.seed = seed;
+    a.F = de->F;
+    a.cr_thr = static_cast<uint64_t>(std::ceil(static_cast<double>(de->CR) * 4294967296.0));
+    a.counters = ctx->counters.as<unsigned long long>();
+
+    if (!ens) {
+        a.items = ctx->items.as<int4>();
+        a.n_items = static_cast<int32_t>(items0.size());
+        a.plain = 1;
+        a.stage = 0;
+        a.ng = de->ng_f;
+        a.Yp = out->params;
+        a.YS = out->S;
+        HIP_OR_FAIL(ctx, ens::launch_search(P, ctx->store_dtype, ctx->window, a, a.n_items, st));
+    } else {
+        float *X = ctx->X.as<float>(), *XS = ctx->XS.as<float>();
+        float *Y = ctx->Y.as<float>(), *YS = ctx->YS.as<float>();
+        a.plain = 0;
+        const int32_t n_stage = 1 + 2 * de->n_cycle;
+        for (int32_t s = 0; s < n_stage; ++s) {
+            a.stage = s;
+            a.forward = (s % 2 == 0) ? 1 : 0;
+            a.ng = s == 0 ? de->ng_f : de->ng_bf;
+            a.items = ctx->items.as<int4>() + (s == 0 ? 0 : items0.size());
+            a.n_items = static_cast<int32_t>(s == 0 ? items0.size() : items_bf.size());
+            a.Xp = X;
+            a.XS = XS;
+            a.Yp = Y;
+            a.YS = YS;
+            for (int32_t k = 0; k < de->n_bucket && k < n_out; ++k) {
+                a.k = k;
+                HIP_OR_FAIL(ctx, ens::launch_search(P, ctx->store_dtype, ctx->window, a, a.n_items, st));
+            }
+            std::swap(X, Y);
+            std::swap(XS, YS);
+        }
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(out->params, X, pbytes, hipMemcpyDeviceToDevice, st));
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(out->S, XS, sbytes, hipMemcpyDeviceToDevice, st));
+    }
+    if (de->polish_steps > 0) {
+        ens::PolishArgs pa{};
+        pa.sv = view_of(ctx, false);
+        pa.cmp_out = ctx->cmp_out.as<int32_t>();
+        pa.n_out = n_out;
+        pa.t_begin = t_begin;
+        pa.n_t = n_t;
+        pa.lo_tab = ctx->lo_tab.as<float>();
+        pa.hi_tab = ctx->hi_tab.as<float>();
+        pa.params = out->params;
+        pa.S = out->S;
+        pa.S_pre = out->S_pre_polish;
+        pa.steps = de->polish_steps;
+        pa.lr = de->polish_lr;
+        pa.counters = ctx->counters.as<unsigned long long>();
+        HIP_OR_FAIL(ctx, ens::launch_polish(P, ctx->store_dtype, ctx->window, pa, st));
+    } else if (out->S_pre_polish) {
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(out->S_pre_polish, out->S, sbytes, hipMemcpyDeviceToDevice, st));
+    }
+    if (de->rescore_fp64 && out->S64) {
+        HIP_OR_FAIL(ctx, ens::launch_eval64_grid(P, ctx->window, view_of(ctx, true), ctx->cmp_out.as<int32_t>(),
+                                                 n_out, t_begin, n_t, out->params, out->S64, st));
+    }
+    unsigned long long cnt[4] = {0, 0, 0, 0};
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(cnt, ctx->counters.p, sizeof cnt, hipMemcpyDeviceToHost, st));
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(st));
+    out->n_evals = static_cast<int64_t>(cnt[0]);
+    out->sum_m = static_cast<int64_t>(cnt[1]);
+    ctx->err.clear();
+    return ENS_OK;
+}
+
+ens_status semblance_eval(ens_ctx *ctx, const ens_candidates *cands, float *S_out, int32_t *M_out)
+{
+    if (!ctx) return ENS_E_INVALID;
+    if (!ctx->bound) return fail(ctx, ENS_E_STATE, "semblance_eval: call ens_bind first");
+    if (!cands || !S_out) return fail(ctx, ENS_E_INVALID, "semblance_eval: null argument");
+    ens_status chk = check_candidates(ctx, cands);
+    if (chk != ENS_OK) return chk;
+    ens::CandView cv{cands->n, cands->cmp, cands->t, cands->params};
+    HIP_OR_FAIL(ctx, ens::launch_eval(ctx->op, ctx->store_dtype, ctx->window, view_of(ctx, false), cv, S_out, M_out,
+                                      ctx->stream));
+    ctx->err.clear();
+    return ENS_OK;
+}
+
+ens_status semblance_eval64(ens_ctx *ctx, const ens_candidates *cands, double *S_out)
+{
+    if (!ctx) return ENS_E_INVALID;
+    if (!ctx->bound) return fail(ctx, ENS_E_STATE, "semblance_eval64: call ens_bind first");
+    if (!cands || !S_out) return fail(ctx, ENS_E_INVALID, "semblance_eval64: null argument");
+    ens_status chk = check_candidates(ctx, cands);
+    if (chk != ENS_OK) return chk;
+    ens::CandView cv{cands->n, cands->cmp, cands->t, cands->params};
+    HIP_OR_FAIL(ctx, ens::launch_eval64(ctx->op, ctx->window, view_of(ctx, true), cv, S_out, ctx->stream));
+    ctx->err.clear();
+    return ENS_OK;
+}
+
+ens_status semblance_backward(ens_ctx *ctx, const ens_candidates *cands, const float *dS, float *dparams_out)
+{
+    if (!ctx) return ENS_E_INVALID;
+    if (!ctx->bound) return fail(ctx, ENS_E_STATE, "semblance_backward: call ens_bind first");
+    if (!cands || !dS || !dparams_out) return fail(ctx, ENS_E_INVALID, "semblance_backward: null argument");
+    ens_status chk = check_candidates(ctx, cands);
+    if (chk != ENS_OK) return chk;
+    ens::CandView cv{cands->n, cands->cmp, cands->t, cands->params};
+    HIP_OR_FAIL(ctx, ens::launch_backward(ctx->op, ctx->store_dtype, ctx->window, view_of(ctx, false), cv, dS,
+                                          dparams_out, ctx->stream));
+    ctx->err.clear();
+    return ENS_OK;
+}
+
+ens_status ens_philox(ens_ctx *ctx, int64_t n, const uint64_t *counters, const uint64_t *key, uint64_t *out)
+{
+    if (!ctx) return ENS_E_INVALID;
+    if (n < 0 || (n > 0 && (!counters || !key || !out))) return fail(ctx, ENS_E_INVALID, "ens_philox: bad argument");
+    HIP_OR_FAIL(ctx, ens::launch_philox(n, counters, key, out, ctx->stream));
+    ctx->err.clear();
+    return ENS_OK;
+}
+
+ens_status ens_de_trial(ens_ctx *ctx, int32_t n_pop, int32_t np, int32_t P, const float *pop, const float *S,
+                        const uint64_t *words, float F, float CR, const float *lo, const float *hi, float *trial)
+{
+    if (!ctx) return ENS_E_INVALID;
+    if (n_pop < 0 || (n_pop > 0 && (!pop || !S || !words || !lo || !hi || !trial)))
+        return fail(ctx, ENS_E_INVALID, "ens_de_trial: bad argument");
+    if (P != 1 && P != 3) return fail(ctx, ENS_E_INVALID, "ens_de_trial: P must be 1 or 3");
+    if (np < 4 || np > ENS_MAX_POP) return fail(ctx, ENS_E_RANGE, "ens_de_trial: np must lie in [4, 64]");
+    if (!finite(F) || !(CR >= 0.f && CR <= 1.f)) return fail(ctx, ENS_E_RANGE, "ens_de_trial: bad F or CR");
+    const uint64_t thr = static_cast<uint64_t>(std::ceil(static_cast<double>(CR) * 4294967296.0));
+    HIP_OR_FAIL(ctx, ens::launch_de_trial(n_pop, np, P, pop, S, words, F, thr, lo, hi, trial, ctx->stream));
+    ctx->err.clear();
+    return ENS_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+
+namespace {
+
+__global__ void k_check_candidates(int64_t n, const int32_t *__restrict__ cmp, const int32_t *__restrict__ t,
+                                   int32_t n_cmp, int32_t nt, int32_t *__restrict__ flag)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (cmp[i] < 0 || cmp[i] >= n_cmp || t[i] < 0 || t[i] >= nt) atomicOr(flag, 1);
+}
+
+ens_status check_candidates(ens_ctx *ctx, const ens_candidates *c)
+{
+    if (c->struct_size < sizeof(ens_candidates)) return fail(ctx, ENS_E_INVALID, "ens_candidates: struct_size too small");
+    if (c->n < 0) return fail(ctx, ENS_E_INVALID, "ens_candidates: n < 0");
+    if (c->n == 0) return ENS_OK;
+    if (!c->cmp || !c->t || !c->params) return fail(ctx, ENS_E_INVALID, "ens_candidates: null array");
+    HIP_OR_FAIL(ctx, ctx->flag.ensure(sizeof(int32_t)));
+    HIP_OR_FAIL(ctx, hipMemsetAsync(ctx->flag.p, 0, sizeof(int32_t), ctx->stream));
+    const unsigned blocks = static_cast<unsigned>((c->n + 255) / 256);
+    hipLaunchKernelGGL(k_check_candidates, dim3(blocks), dim3(256), 0, ctx->stream, c->n, c->cmp, c->t, ctx->n_cmp,
+                       ctx->nt, ctx->flag.as<int32_t>());
+    HIP_OR_FAIL(ctx, hipGetLastError());
+    int32_t flag = 0;
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(&flag, ctx->flag.p, sizeof flag, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+    if (flag) return fail(ctx, ENS_E_RANGE, "ens_candidates: a CMP or time index is out of range");
+    return ENS_OK;
+}
+
+}  // namespace

@@ -1,0 +1,305 @@
+// Device building blocks shared by every kernel of libens (gfx950, wave64).
+//
+//  - Philox-4x64-10 counter-based generator (Salmon et al., SC'11).
+//  - Trace store layout: each trace row holds PAD zero samples, the nt
+//    samples, then zeros up to the row stride, so a window read around any
+//    participating traveltime stays inside the row and reads 0 outside the
+//    record without a bounds test.
+//  - accum_trace(): traveltime of one (candidate, trace) pair, linear
+//    interpolation of the W+1 samples around it and accumulation of the
+//    window sums s_k and the energy E (section "Traveltime parameter search":
+//    the objective's cost is the window length times the aperture traces).
+//
+// The traveltime is evaluated in sample units relative to the output time
+// n0 (exact integer): with tau^2 = q = n0^2 + mo, the moveout
+// dtau = tau - n0 = mo / (tau + n0) is formed without cancellation, and the
+// sample index n0 + floor(dtau) never goes through a rounded tau.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ens {
+
+constexpr int PAD = 8;     // zero samples before and after each stored trace
+constexpr int WAVE = 64;
+
+// ---------------------------------------------------------------------------
+// Philox-4x64-10
+
+__device__ __forceinline__ void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                              uint64_t k0, uint64_t k1, uint64_t out[4])
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+        const uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += W0;
+        k1 += W1;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+// ---------------------------------------------------------------------------
+// storage element types
+
+enum { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2 };
+
+template <int DT> struct Store;
+template <> struct Store<DT_F32> { using T = float; };
+template <> struct Store<DT_F16> { using T = uint16_t; };
+template <> struct Store<DT_BF16> { using T = uint16_t; };
+
+__device__ __forceinline__ float bf16_bits_to_f32(uint32_t b) { return __uint_as_float(b << 16); }
+__device__ __forceinline__ float f16_bits_to_f32(uint32_t b)
+{
+    return static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(b)));
+}
+
+typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
+typedef float f2u __attribute__((ext_vector_type(2), aligned(4)));
+
+// Load N consecutive stored samples starting at p as binary32.
+template <int DT, int N>
+__device__ __forceinline__ void load_window(const typename Store<DT>::T *__restrict__ p, float *u)
+{
+    if constexpr (DT == DT_F32) {
+        int k = 0;
+#pragma unroll
+        for (; k + 4 <= N; k += 4) {
+            f4u v = *reinterpret_cast<const f4u *>(p + k);
+            u[k] = v.x; u[k + 1] = v.y; u[k + 2] = v.z; u[k + 3] = v.w;
+        }
+        if constexpr (N % 4 >= 2) {
+            f2u v = *reinterpret_cast<const f2u *>(p + k);
+            u[k] = v.x; u[k + 1] = v.y;
+            k += 2;
+        }
+        if constexpr (N % 2 == 1) u[k] = p[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            const uint32_t b = p[k];
+            u[k] = DT == DT_F16 ? f16_bits_to_f32(b) : bf16_bits_to_f32(b);
+        }
+    }
+}
+
+// Per-trace geometry, one 16-byte record per trace.
+struct TraceMeta {
+    float cx;      // CMP position c * dx
+    float h2;      // h^2 (binary32)
+    int32_t cmp;   // CMP index c
+    float h;       // full offset
+};
+
+// Candidate constants in sample units: mo = al*dm + be*dm^2 + ga*h^2.
+template <typename R>
+struct Cand {
+    R al, be, ga;
+    R As;              // A / dt (CRS), 0 for CMP
+    R n0f, n0sq;       // n0, n0^2
+    R lo_lim, hi_lim;  // participation: -n0 <= dtau <= nt-1-n0
+    R jx;              // output CMP position j * dx
+    int32_t n0, j, ap; // output time index, output CMP, half-aperture (CMPs)
+};
+
+// Operator constants.  CMP: t^2 = t0^2 + C h^2.  CRS: t^2 = (t0 + A dm)^2 +
+// B t0 dm^2 + C t0 h^2.  Divided by dt^2 with t0 = n0 dt.
+template <int OP, typename R>
+__device__ __forceinline__ Cand<R> make_cand(const R *p, int32_t n0, int32_t j, int32_t ap, int32_t nt,
+                                             R dt, R dx)
+{
+    Cand<R> c;
+    const R inv_dt = R(1) / dt;
+    const R n0f = static_cast<R>(n0);
+    if constexpr (OP == 1) {
+        c.al = R(0);
+        c.be = R(0);
+        c.ga = p[0] * inv_dt * inv_dt;
+        c.As = R(0);
+    } else {
+        const R As = p[0] * inv_dt;            // A / dt  (samples per metre)
+        c.al = R(2) * n0f * As;
+        c.be = As * As + p[1] * n0f * inv_dt;  // (A/dt)^2 + B t0 / dt^2
+        c.ga = p[2] * n0f * inv_dt;            // C t0 / dt^2
+        c.As = As;
+    }
+    c.n0f = n0f;
+    c.n0sq = n0f * n0f;
+    c.lo_lim = -n0f;
+    c.hi_lim = static_cast<R>(nt - 1 - n0);
+    c.jx = static_cast<R>(j) * dx;
+    c.n0 = n0;
+    c.j = j;
+    c.ap = ap;
+    return c;
+}
+
+template <int W, typename R>
+struct Acc {
+    R s[W];
+    R E;
+    int32_t M;
+    __device__ __forceinline__ void reset()
+    {
+#pragma unroll
+        for (int k = 0; k < W; ++k) s[k] = R(0);
+        E = R(0);
+        M = 0;
+    }
+};
+
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double fast_sqrt(double x) { return __builtin_sqrt(x); }
+__device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
+
+// Traveltime of (candidate, trace): participation flag, sample index n and
+// fraction f.  q < 0, dtau out of range, or the trace's CMP outside the
+// candidate's aperture: not participating.
+template <typename R>
+struct TT {
+    bool ok;
+    int32_t n;
+    R f;
+    R tau_abs;    // sqrt(q) in samples (for the adjoint)
+    R dm;         // midpoint displacement (m)
+};
+
+template <typename R>
+__device__ __forceinline__ TT<R> traveltime(const Cand<R> &c, const TraceMeta &tm)
+{
+    TT<R> r;
+    const R dm = static_cast<R>(tm.cx) - c.jx;
+    const R dm2 = dm * dm;
+    R h2;
+    if constexpr (sizeof(R) == 8) {
+        h2 = static_cast<R>(tm.h) * static_cast<R>(tm.h);
+    } else {
+        h2 = tm.h2;
+    }
+    const R mo = __builtin_fma(c.ga, h2, __builtin_fma(c.be, dm2, c.al * dm));
+    const R q = c.n0sq + mo;
+    const R tau = fast_sqrt(q > R(0) ? q : R(0));
+    const R den = tau + c.n0f;
+    const R dtau = den > R(0) ? mo * fast_rcp(den) : R(0);
+    const int32_t dc = tm.cmp - c.j;
+    const bool in_ap = dc <= c.ap && -dc <= c.ap;
+    r.ok = in_ap && (q >= R(0)) && (dtau >= c.lo_lim) && (dtau <= c.hi_lim);
+    const R fl = __builtin_floor(dtau);
+    r.f = dtau - fl;
+    r.n = r.ok ? c.n0 + static_cast<int32_t>(fl) : 0;
+    r.tau_abs = tau;
+    r.dm = dm;
+    return r;
+}
+
+// Accumulate one trace into the window sums.  row: the trace's sample 0.
+template <int DT, int W, bool SCALED, typename R>
+__device__ __forceinline__ void accum_trace(Acc<W, R> &acc, const Cand<R> &c, const TraceMeta &tm,
+                                            const typename Store<DT>::T *__restrict__ row,
+                                            float scale)
+{
+    const TT<R> tt = traveltime(c, tm);
+    R wb = tt.ok ? tt.f : R(0);
+    R wa = tt.ok ? R(1) - tt.f : R(0);
+    if constexpr (SCALED) {
+        wa *= static_cast<R>(scale);
+        wb *= static_cast<R>(scale);
+    }
+    acc.M += tt.ok ? 1 : 0;
+    float u[W + 1];
+    load_window<DT, W + 1>(row + (tt.n - W / 2), u);
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        const R a = __builtin_fma(wb, static_cast<R>(u[k + 1]), wa * static_cast<R>(u[k]));
+        acc.s[k] += a;
+        acc.E = __builtin_fma(a, a, acc.E);
+    }
+}
+
+template <int W, typename R>
+__device__ __forceinline__ R finish_semblance(const Acc<W, R> &acc)
+{
+    R N = R(0);
+#pragma unroll
+    for (int k = 0; k < W; ++k) N = __builtin_fma(acc.s[k], acc.s[k], N);
+    if (acc.M > 0 && acc.E > R(0)) return N / (static_cast<R>(acc.M) * acc.E);
+    return R(0);
+}
+
+// ---------------------------------------------------------------------------
+// evolution step (binary32 arithmetic written out operation by operation;
+// the library is built without floating-point contraction)
+
+struct TrialDraw {
+    uint32_t r1, r2, jr;
+    bool take[3];
+};
+
+// Indices and crossover decisions of one slot from its generator block.
+__device__ __forceinline__ TrialDraw trial_draw(const uint64_t w[4], int32_t i, int32_t np, int32_t P,
+                                                uint64_t cr_thr)
+{
+    TrialDraw d;
+    uint32_t r1 = static_cast<uint32_t>(((w[0] >> 32) * static_cast<uint64_t>(np - 1)) >> 32);
+    if (r1 >= static_cast<uint32_t>(i)) r1 += 1;
+    uint32_t r2 = static_cast<uint32_t>(((w[0] & 0xffffffffULL) * static_cast<uint64_t>(np - 2)) >> 32);
+    const uint32_t ui = static_cast<uint32_t>(i);
+    const uint32_t ex_lo = ui < r1 ? ui : r1, ex_hi = ui < r1 ? r1 : ui;
+    if (r2 >= ex_lo) r2 += 1;
+    if (r2 >= ex_hi) r2 += 1;
+    d.r1 = r1;
+    d.r2 = r2;
+    d.jr = static_cast<uint32_t>(((w[1] >> 32) * static_cast<uint64_t>(P)) >> 32);
+    const uint64_t cr[3] = {w[1] & 0xffffffffULL, w[2] >> 32, w[2] & 0xffffffffULL};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) d.take[k] = cr[k] < cr_thr || static_cast<uint32_t>(k) == d.jr;
+    return d;
+}
+
+// Mutant coordinate, repaired into [lo, hi] by the midpoint toward the parent.
+__device__ __forceinline__ float mutant(float xi, float xb, float xr1, float xr2, float F, float lo,
+                                        float hi)
+{
+    const float t1 = xb - xi;
+    const float t2 = xr1 - xr2;
+    const float m1 = F * t1;
+    const float m2 = F * t2;
+    float v = xi + m1;
+    v = v + m2;
+    if (v < lo)
+        v = (lo + xi) * 0.5f;
+    else if (v > hi)
+        v = (hi + xi) * 0.5f;
+    return v;
+}
+
+__device__ __forceinline__ float init_coord(uint64_t w, float lo, float hi)
+{
+    const float u = static_cast<float>(w >> 40) * 0x1p-24f;
+    const float range = hi - lo;
+    const float step = u * range;
+    return lo + step;
+}
+
+// XCD-aware block order: the hardware deals consecutive workgroups round-robin
+// to the 8 XCDs; give each XCD a contiguous run of work items so that the
+// traces those items gather stay in that XCD's L2.
+__device__ __forceinline__ int32_t xcd_remap(int32_t bid, int32_t nblocks)
+{
+    constexpr int NX = 8;
+    const int32_t per = nblocks / NX, rem = nblocks % NX;
+    const int32_t x = bid % NX, local = bid / NX;
+    return x * per + (x < rem ? x : rem) + local;
+}
+
+}  // namespace ens

@@ -1,0 +1,88 @@
+// Argument blocks and launch wrappers shared by kernels.hip and api.cpp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ens {
+
+struct TraceMeta;
+
+// Bound trace store and per-time tables.
+struct StoreView {
+    const void *store;        // [n_tr][ld] padded rows, sample 0 at column PAD
+    int64_t ld;
+    const float *scale;       // [n_tr] per-trace scale, or nullptr for binary32 storage
+    const TraceMeta *meta;    // [n_tr]
+    const int64_t *cmp_ptr;   // [n_cmp+1]
+    int32_t n_cmp;
+    int32_t nt;
+    float dt, dx;
+    const int32_t *ap_tab;    // [nt] half-aperture per time index
+};
+
+struct CandView {
+    int64_t n;
+    const int32_t *cmp;
+    const int32_t *t;
+    const float *params;      // [n][P]
+};
+
+// One launch of the evolution: either every sample of the grid evolving on
+// its own (plain), or one trace step of an ENS sweep over all buckets.
+struct SearchArgs {
+    StoreView sv;
+    const int32_t *cmp_out;   // [n_out] output CMPs
+    int32_t n_out, t_begin, n_t;
+    const float *lo_tab, *hi_tab;  // [nt][3] per-time boxes
+    const int4 *items;        // work items {output index or bucket, first t, samples, NP}
+    int32_t n_items;
+    int32_t plain, stage, k, forward, n_bucket, ng, inject, nsl;
+    uint64_t seed;
+    float F;
+    uint64_t cr_thr;          // crossover draw threshold ceil(CR 2^32)
+    const float *Xp, *XS;     // previous stage state [n_out][n_t][P], [n_out][n_t]
+    float *Yp, *YS;           // this stage's state
+    unsigned long long *counters;  // [0] evaluations, [1] participating traces
+};
+
+struct PolishArgs {
+    StoreView sv;
+    const int32_t *cmp_out;
+    int32_t n_out, t_begin, n_t;
+    const float *lo_tab, *hi_tab;
+    float *params;            // [n_out][n_t][P] in/out
+    float *S;                 // [n_out][n_t] in/out
+    float *S_pre;             // optional copy of the incoming S
+    int32_t steps;
+    float lr;
+    unsigned long long *counters;  // [2] forward evaluations, [3] adjoint passes
+};
+
+// launch wrappers (return hipSuccess or the launch error)
+hipError_t launch_store_f32(const float *src, int64_t ld_in, int64_t n_tr, int32_t nt, int64_t ld,
+                            float *dst, hipStream_t s);
+hipError_t launch_quantize(const float *src, int64_t ld_in, int64_t n_tr, int32_t nt, int32_t dtype,
+                           uint16_t *dst, int64_t ld_out, int32_t col0, float *scale,
+                           hipStream_t s);
+hipError_t launch_eval(int op, int dtype, int window, const StoreView &sv, const CandView &cv,
+                       float *S, int32_t *M, hipStream_t s);
+hipError_t launch_eval64(int op, int window, const StoreView &sv_f32, const CandView &cv, double *S,
+                         hipStream_t s);
+hipError_t launch_eval64_grid(int op, int window, const StoreView &sv_f32, const int32_t *cmp_out,
+                              int32_t n_out, int32_t t_begin, int32_t n_t, const float *params,
+                              double *S, hipStream_t s);
+hipError_t launch_backward(int op, int dtype, int window, const StoreView &sv, const CandView &cv,
+                           const float *dS, float *g, hipStream_t s);
+hipError_t launch_search(int op, int dtype, int window, const SearchArgs &a, int32_t n_blocks,
+                         hipStream_t s);
+hipError_t launch_polish(int op, int dtype, int window, const PolishArgs &a, hipStream_t s);
+hipError_t launch_philox(int64_t n, const uint64_t *ctr, const uint64_t *key, uint64_t *out,
+                         hipStream_t s);
+hipError_t launch_de_trial(int32_t n_pop, int32_t np, int32_t P, const float *pop, const float *S,
+                           const uint64_t *words, float F, uint64_t cr_thr, const float *lo,
+                           const float *hi, float *trial, hipStream_t s);
+
+bool window_supported(int window);
+
+}  // namespace ens
