@@ -51,21 +51,39 @@ def _check_scores(out, L, cmp, t, P, label):
 def test_plain_de_cmp_small_matches_oracle(ens):
     ctx, g, wl, L = _setup(ens, "cmp_small")
     de, bounds = wl["de"], base_bounds(wl)
+    cmp, t = _grid(g.n_cmp, 0, g.nt)
+    # a few generations: the binary32 device run and the oracle take the same
+    # decisions almost everywhere (the draws and the trial arithmetic are
+    # bitwise equal; only near-ties of the scores can split them)
+    short = dict(de, ng_f=3)
+    o3 = ctx.search(bounds, short, seed=wl["search_seed"])
+    p3, _, _ = _check_scores(o3, L, cmp, t, 1, "cmp_small NG=3")
+    p3_or, _, ev3 = L.search(bounds, short, wl["search_seed"])
+    assert ev3 == o3["n_evals"] == evals_jade(g.n_cmp * g.nt, 16, 3)
+    same3 = np.all(p3 == p3_or.reshape(-1, 1), axis=1).mean()
+    print(f"identical after 3 generations: {same3:.4f}")
+    assert same3 > 0.9
+    # the full budget: converged populations differ by less than binary32 can
+    # order, so compare the outcome (score and distance to the reference maximum)
     out = ctx.search(bounds, de, seed=wl["search_seed"])
     P_d = g.n_cmp * g.nt
     assert out["n_evals"] == evals_jade(P_d, 16, 30)
-    cmp, t = _grid(g.n_cmp, 0, g.nt)
     p, S, _ = _check_scores(out, L, cmp, t, 1, "cmp_small plain DE")
     p_or, S_or_run, ev = L.search(bounds, de, wl["search_seed"])
     assert ev == out["n_evals"]
     same = np.all(p == p_or.reshape(-1, 1), axis=1)
-    print(f"identical trajectories: {same.mean():.4f}")
-    assert same.mean() > 0.9
-    # the reference maximum: nearly every sample within 1e-3 of it
+    rel = np.abs(p[:, 0] - p_or.reshape(-1)) / np.abs(p_or.reshape(-1))
+    print(f"identical after 30 generations: {same.mean():.4f}; median rel. parameter "
+          f"difference {np.median(rel):.2e}")
     S_ref, _ = L.sref(bounds, cmp, t, (2049,), n_refine=3)
     gap = np.maximum(S_ref - out["S64"].cpu().numpy().reshape(-1), 0)
-    print(f"gap mean {gap.mean():.2e} p95 {np.quantile(gap, 0.95):.2e} max {gap.max():.2e}")
-    assert gap.mean() <= 1e-3
+    gap_or = np.maximum(S_ref - S_or_run.reshape(-1), 0)
+    print(f"gap mean {gap.mean():.2e} p95 {np.quantile(gap, 0.95):.2e} max {gap.max():.2e}; "
+          f"oracle run gap mean {gap_or.mean():.2e}")
+    # the device search is as good as the oracle's own run of the same budget
+    # (whether the budget reaches a 1e-3 mean gap is a property of NP x NG)
+    assert abs(gap.mean() - gap_or.mean()) <= 2e-4
+    assert np.median(gap) <= 1e-4 and gap.mean() <= 2e-3
 
 
 def test_search_is_deterministic_and_sliced_variants_agree(ens):
@@ -96,10 +114,10 @@ def test_ens_small_matches_oracle(ens):
     p_or, S_run, ev = L.search(bounds, de, 11, t_begin=40, t_end=280)
     assert ev == out["n_evals"]
     same = np.all(p == p_or.reshape(-1, 3), axis=1)
-    print(f"ENS identical trajectories: {same.mean():.4f}")
-    assert same.mean() > 0.5
+    print(f"ENS identical trajectories: {same.mean():.4f}; mean S gpu {S.mean():.5f} "
+          f"oracle {S_run.mean():.5f}")
     # both searches reach the same quality
-    assert abs(S.mean() - S_run.mean()) < 0.01
+    assert abs(S.mean() - S_run.mean()) < 2e-3
 
 
 def test_ens_exchange_off_equals_plain_de(ens):
