@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Throughput of the ENS traveltime-parameter search on one MI355X.
+
+One step = one pass of the whole path over the workload: bind the
+device-resident traces into the library's store, then the search (initial
+populations, every generation of every ENS stage, the neighbour exchange) and
+the binary64 re-scoring of every winner.  Prints one JSON line.
+
+Workloads (synthetic Ricker gathers, synth.WORKLOADS): crs_ens (default:
+256 CMPs x 48 offsets x 1000 samples, CRS operator, NP 32 x NG 80 + ENS),
+cmp_small, crs_uneven, crs_precision, crs_diff.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "semblance evals/s & ZO samples/s at <=1e-3 semblance gap; % of HBM peak"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_PEAK_TFLOPS = 157.3       # MI355X vector binary32 (counts packed dual-FMA issue)
+CU, CLOCK_GHZ = 256, 2.4
+
+
+def flops_per_pair(op, window):
+    """Arithmetic of the definition per (candidate, participating trace).
+
+    Traveltime with per-candidate constants folded (mo = al dm + be dm^2 +
+    ga h^2: 5; q = n0^2 + mo: 1; sqrt: 1; dtau = mo / (tau + n0): 2; floor
+    and fraction: 2) = 11 (CMP: mo = ga h^2: 1 -> 7); per window sample the
+    interpolation (1-f) u_k + f u_k+1 (3) and the sums s_k += a, E += a^2 (3),
+    plus 1 for 1-f.
+    """
+    tt = 11 if op == 3 else 7
+    return tt + 6 * window + 1
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="crs_ens")
+    ap.add_argument("--store", default=None, help="f32, f16 or bf16 (default: the workload's)")
+    ap.add_argument("--waves", type=int, default=0, help="trace slices per population (0: auto)")
+    ap.add_argument("--graph", action="store_true", help="replay the trace steps as a HIP graph")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-gap", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(g, wl, de, bounds):
+    """The oracle (binary64 C, OpenMP) on a bounded sample of the workload."""
+    import numpy as np
+
+    import oracle
+    L = oracle.Line.from_gather(g, wl["window"], wl["op"], wl["ap_lo"], wl["ap_hi"])
+    if wl["de"]["ens_enabled"]:
+        mid = g.n_cmp // 2
+        cmp_out = np.arange(mid - 2, mid + 2, dtype=np.int32)
+        t0, t1 = g.nt // 4, g.nt // 4 + min(500, g.nt // 2)
+        de_s = dict(de, n_bucket=4)
+        what = f"ENS over CMPs {cmp_out[0]}..{cmp_out[-1]} (one 4-CMP bucket) x t {t0}..{t1 - 1}"
+    else:
+        cmp_out = np.arange(0, min(4, g.n_cmp), dtype=np.int32)
+        t0, t1 = 0, g.nt
+        de_s = de
+        what = f"plain DE over CMPs 0..{cmp_out[-1]} x all t"
+    start = time.perf_counter()
+    _, _, ev = L.search(bounds, de_s, wl["search_seed"], cmp_out=cmp_out, t_begin=t0, t_end=t1)
+    sec = time.perf_counter() - start
+    n = cmp_out.size * (t1 - t0)
+    threads = oracle.lib().or_num_threads()
+    return {"value": round(n / sec, 3), "unit": "ZO samples/s", "cores": int(threads),
+            "kind": "oracle", "sample": f"{what}: {n} ZO samples, {ev} evaluations, "
+            f"{sec:.1f} s, {ev / sec:.4g} evals/s"}
+
+
+def gap_stats(name, S64, nt, g):
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", f"sref_{name}.npz")
+    if not os.path.exists(path):
+        return None
+    ref = np.load(path)
+    fp = float((g.traces.astype(np.float64) ** 2).sum())
+    if abs(fp / float(ref["fingerprint"]) - 1.0) > 1e-9:
+        return {"error": "reference maxima were made for other data"}
+    found = S64.reshape(-1)[ref["cmp"].astype(np.int64) * nt + ref["t"]]
+    gap = np.maximum(ref["S_ref"] - found, 0.0)
+    return {"n": int(gap.size), "mean": float(gap.mean()), "p50": float(np.median(gap)),
+            "p95": float(np.quantile(gap, 0.95)), "max": float(gap.max()),
+            "frac_le_1e-3": float((gap <= 1e-3).mean()),
+            "mean_S": float(found.mean()), "rms_S": float(np.sqrt((found ** 2).mean()))}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        msg = ("this build runs on one GPU only: the search shards by bucket across GPUs "
+               "by design but no multi-GPU path is built; run with --gpus 1")
+        print(json.dumps({"metric": METRIC, "error": msg, "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2304_11399_amd as ens
+    from synth import base_bounds, make_workload
+
+    torch.cuda.set_device(0)
+    g, wl = make_workload(args.workload)
+    store = args.store or wl["store"]
+    de, bounds = dict(wl["de"]), base_bounds(wl)
+    stream = torch.cuda.Stream() if args.graph else torch.cuda.current_stream()
+    with torch.cuda.stream(stream):
+        ctx = ens.Context(stream)
+        ctx.set_tuning(waves_per_sample_group=args.waves, use_graph=int(args.graph))
+        traces = torch.from_numpy(g.traces).cuda()
+        P_d = g.n_cmp * g.nt
+
+        def step():
+            ctx.bind(traces, g.cmp_ptr, g.offset, g.dt, g.dx, wl["op"], wl["window"], wl["ap_lo"],
+                     wl["ap_hi"], store=store)
+            return ctx.search(bounds, de, wl["search_seed"], rescore_fp64=True)
+
+        for _ in range(args.warmup):
+            out = step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            out = step()
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        ms_step = 1e3 * sec / args.steps
+        evals = out["n_evals"]
+        S64 = out["S64"].cpu().numpy()
+
+        # one more step with per-launch event timing, outside the timed region
+        ctx.set_tuning(waves_per_sample_group=args.waves, collect_timing=1)
+        step()
+        st = ctx.stats()
+        ctx.set_tuning(waves_per_sample_group=args.waves, use_graph=int(args.graph))
+
+    if wl["de"]["ens_enabled"]:
+        expect = ens.evals_ens(P_d, de["np_lo"], de["ng_f"], de["np_bf"], de["ng_bf"],
+                               de["n_cycle"])
+    else:
+        expect = ens.evals_jade(P_d, de["np_lo"], de["ng_f"])
+    assert de["np_lo"] != de["np_hi"] or evals == expect, (evals, expect)
+
+    # roofline of the dominant kernel: the exploration trace-step launches
+    ex = st["explore"]
+    elem = 4 if store == "f32" else 2
+    W = wl["window"]
+    per_launch_s = ex["device_ms"] / 1e3 / ex["launches"]
+    bytes_per_launch = ex["sum_m"] * (W + 1) * elem / ex["launches"]
+    flops_per_launch = ex["sum_m"] * flops_per_pair(wl["op"], W) / ex["launches"]
+    gbs = bytes_per_launch / per_launch_s / 1e9
+    tflops = flops_per_launch / per_launch_s / 1e12
+    roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": FP32_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(tflops / FP32_PEAK_TFLOPS, 4), "traffic": None,
+            "kernel": f"k_search<{wl['op']},{ {'f32': 0, 'f16': 1, 'bf16': 2}[store]},{W},0>",
+            "launches": ex["launches"], "avg_launch_ms": round(ex["device_ms"] / ex["launches"], 4),
+            "algorithmic_gather": {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                   "frac": round(gbs / HBM_PEAK_GBS, 4)}}
+
+    gap = None if args.no_gap else gap_stats(args.workload, S64, g.nt, g)
+    line = {
+        "metric": METRIC,
+        "value": round(P_d * args.steps / sec, 3),
+        "unit": "ZO samples/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": store, "data": "synthetic",
+        "config": {"workload": args.workload, "n_cmp": g.n_cmp, "offsets": int(g.cmp_ptr[1]),
+                   "nt": g.nt, "op": "CRS" if wl["op"] == 3 else "CMP", "window": W,
+                   "aperture": [wl["ap_lo"], wl["ap_hi"]], "np": [de["np_lo"], de["np_hi"]],
+                   "ng": de["ng_f"], "ens": bool(de["ens_enabled"]), "n_cycle": de["n_cycle"],
+                   "n_bucket": de["n_bucket"], "polish_steps": de["polish_steps"],
+                   "zo_samples": P_d, "parallelism": "1 GPU"},
+        "evals_per_s": round(evals * args.steps / sec, 1),
+        "evals_per_step": evals,
+        "gap": gap,
+        "gap_ok": None if not gap or "mean" not in gap else bool(gap["mean"] <= 1e-3),
+        "roofline": roof,
+        "stats": st,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(g, wl, de, bounds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -176,7 +176,23 @@ typedef struct {
     uint32_t struct_size;
     int32_t waves_per_sample_group;  /* trace slices per population (1, 2, 4, 8) */
     int32_t use_graph;               /* 1: replay the trace-step launches as a HIP graph */
+    int32_t collect_timing;          /* 1: time every search launch with HIP events */
 } ens_tuning;
+
+/* Work and device time of the last ens_search, per kernel kind:
+ * [0] exploration launches (plain evolution, or ENS stage 0),
+ * [1] exploitation launches (ENS backward/forward stages),
+ * [2] gradient polish, [3] binary64 re-scoring.
+ * evals / sum_m: semblance evaluations and participating traces summed over
+ * them (for [2]: forward evaluations of the polish).  device_ms is the sum of
+ * the launches' event-timed durations when collect_timing was set, else 0. */
+typedef struct {
+    uint32_t struct_size;
+    int64_t launches[4];
+    int64_t evals[4];
+    int64_t sum_m[4];
+    double device_ms[4];
+} ens_stats;
 
 /* ---- context ----------------------------------------------------------- */
 
@@ -189,6 +205,8 @@ const char *ens_last_error(const ens_ctx *ctx);
 /* Library version string. */
 const char *ens_version(void);
 ens_status ens_set_tuning(ens_ctx *ctx, const ens_tuning *tuning);
+/* Statistics of the last successful ens_search on ctx (host struct). */
+ens_status ens_last_stats(const ens_ctx *ctx, ens_stats *out);
 
 /* ---- data --------------------------------------------------------------- */
 

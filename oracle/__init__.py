@@ -57,6 +57,7 @@ def lib():
         L = C.CDLL(LIB_PATH)
         P = C.c_void_p
         L.or_philox4x64_10.argtypes = [P, P, P]
+        L.or_num_threads.restype = C.c_int32
         L.or_aperture.argtypes = [C.POINTER(_Line), C.c_int32]
         L.or_aperture.restype = C.c_int32
         L.or_pop_size.argtypes = [C.POINTER(_DeCfg), C.c_int32, C.c_int32]

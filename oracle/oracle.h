@@ -54,6 +54,9 @@ typedef struct {
     int32_t objective;      /* 0 semblance; 1 sphere mock; 2 needle mock */
 } or_de_cfg;
 
+/* OpenMP threads the oracle's parallel loops use. */
+int32_t or_num_threads(void);
+
 /* counter-based generator: Philox-4x64 with 10 rounds (Salmon et al., SC'11) */
 void or_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
 

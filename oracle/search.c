@@ -40,10 +40,22 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #include "oracle.h"
 
 #define MAXNP 64
+
+int32_t or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 int32_t or_pop_size(const or_de_cfg *cfg, int32_t nt, int32_t n0)
 {

@@ -80,7 +80,16 @@ class Candidates(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("waves_per_sample_group", C.c_int32),
-                ("use_graph", C.c_int32)]
+                ("use_graph", C.c_int32), ("collect_timing", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("launches", C.c_int64 * 4),
+                ("evals", C.c_int64 * 4), ("sum_m", C.c_int64 * 4),
+                ("device_ms", C.c_double * 4)]
+
+
+STAT_KINDS = ("explore", "exploit", "polish", "rescore64")
 
 
 def _sized(cls, **kw):
@@ -100,6 +109,7 @@ _SIGS = {
     "ens_ctx_destroy": (None, [_P]),
     "ens_last_error": (C.c_char_p, [_P]),
     "ens_set_tuning": (C.c_int, [_P, C.POINTER(Tuning)]),
+    "ens_last_stats": (C.c_int, [_P, C.POINTER(Stats)]),
     "ens_bind": (C.c_int, [_P, C.POINTER(Traces), C.POINTER(Geometry), C.POINTER(SemCfg)]),
     "ens_quantize": (C.c_int, [_P, _P, C.c_int64, C.c_int32, C.c_int64, C.c_int32, _P, _P]),
     "ens_search": (C.c_int, [_P, C.POINTER(T0Grid), C.POINTER(Bounds), C.POINTER(DeCfg),
@@ -174,9 +184,19 @@ class Context:
     def last_error(self):
         return self._lib.ens_last_error(self._h).decode()
 
-    def set_tuning(self, waves_per_sample_group=0, use_graph=0):
-        t = _sized(Tuning, waves_per_sample_group=waves_per_sample_group, use_graph=use_graph)
+    def set_tuning(self, waves_per_sample_group=0, use_graph=0, collect_timing=0):
+        t = _sized(Tuning, waves_per_sample_group=waves_per_sample_group, use_graph=use_graph,
+                   collect_timing=collect_timing)
         self._check(self._lib.ens_set_tuning(self._h, C.byref(t)))
+
+    def stats(self):
+        """Per-kind launches, evaluations, participating traces and device ms of
+        the last search."""
+        st = _sized(Stats)
+        self._check(self._lib.ens_last_stats(self._h, C.byref(st)))
+        return {k: dict(launches=int(st.launches[i]), evals=int(st.evals[i]),
+                        sum_m=int(st.sum_m[i]), device_ms=float(st.device_ms[i]))
+                for i, k in enumerate(STAT_KINDS)}
 
     # -------------------------------------------------------------- data
     def bind(self, traces, cmp_ptr, offset, dt, dx, op, window, ap_lo=0, ap_hi=None,

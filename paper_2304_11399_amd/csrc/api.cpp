@@ -61,8 +61,30 @@ struct ens_ctx {
     DevBuf store, master, scale, meta, cmp_ptr, ap_tab;
     // search workspace
     DevBuf lo_tab, hi_tab, items, X, XS, Y, YS, counters, cmp_out, flag;
+    // statistics of the last search, launch timing events
+    ens_stats stats{};
+    std::vector<hipEvent_t> events;
+    // captured trace-step sequence of the last ENS search (replayed when the
+    // next search issues exactly the same launches)
+    struct Launch {
+        ens::SearchArgs a;
+        int32_t kind, n_blocks;
+    };
+    std::vector<Launch> graph_seq;
+    hipGraphExec_t graph_exec = nullptr;
+    hipGraph_t graph = nullptr;
+    void drop_graph()
+    {
+        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        graph_exec = nullptr;
+        graph = nullptr;
+        graph_seq.clear();
+    }
     ~ens_ctx()
     {
+        drop_graph();
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
         for (DevBuf *b : {&store, &master, &scale, &meta, &cmp_ptr, &ap_tab, &lo_tab, &hi_tab, &items,
                           &X, &XS, &Y, &YS, &counters, &cmp_out, &flag})
             b->release();
@@ -167,8 +189,19 @@ ens_status ens_set_tuning(ens_ctx *ctx, const ens_tuning *t)
     const int w = t->waves_per_sample_group;
     if (!(w == 0 || w == 1 || w == 2 || w == 4 || w == 8))
         return fail(ctx, ENS_E_RANGE, "waves_per_sample_group must be 0, 1, 2, 4 or 8 (got %d)", w);
+    if (t->use_graph && t->collect_timing)
+        return fail(ctx, ENS_E_INVALID, "use_graph and collect_timing exclude each other");
     ctx->tuning = *t;
     ctx->err.clear();
+    return ENS_OK;
+}
+
+ens_status ens_last_stats(const ens_ctx *ctx, ens_stats *out)
+{
+    if (!ctx || !out) return ENS_E_INVALID;
+    if (out->struct_size < sizeof(ens_stats)) return ENS_E_INVALID;
+    *out = ctx->stats;
+    out->struct_size = sizeof(ens_stats);
     return ENS_OK;
 }
 
@@ -339,7 +372,7 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
     HIP_OR_FAIL(ctx, ctx->hi_tab.ensure(hi.size() * sizeof(float)));
     HIP_OR_FAIL(ctx, ctx->cmp_out.ensure(cmp_out.size() * sizeof(int32_t)));
     HIP_OR_FAIL(ctx, ctx->items.ensure((items0.size() + items_bf.size()) * sizeof(int4)));
-    HIP_OR_FAIL(ctx, ctx->counters.ensure(4 * sizeof(unsigned long long)));
+    HIP_OR_FAIL(ctx, ctx->counters.ensure(8 * sizeof(unsigned long long)));
     if (ens) {
         HIP_OR_FAIL(ctx, ctx->X.ensure(pbytes));
         HIP_OR_FAIL(ctx, ctx->Y.ensure(pbytes));
@@ -355,8 +388,9 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
     if (!items_bf.empty())
         HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->items.as<int4>() + items0.size(), items_bf.data(),
                                         items_bf.size() * sizeof(int4), hipMemcpyHostToDevice, st));
-    HIP_OR_FAIL(ctx, hipMemsetAsync(ctx->counters.p, 0, 4 * sizeof(unsigned long long), st));
+    HIP_OR_FAIL(ctx, hipMemsetAsync(ctx->counters.p, 0, 8 * sizeof(unsigned long long), st));
 
+    float *final_params = nullptr, *final_S = nullptr;
     ens::SearchArgs a{};
     a.sv = view_of(ctx, false);
     a.cmp_out = ctx->cmp_out.as<int32_t>();
@@ -373,6 +407,8 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
     a.cr_thr = static_cast<uint64_t>(std::ceil(static_cast<double>(de->CR) * 4294967296.0));
     a.counters = ctx->counters.as<unsigned long long>();
 
+    // launch sequence of the evolution
+    std::vector<ens_ctx::Launch> seq;
     if (!ens) {
         a.items = ctx->items.as<int4>();
         a.n_items = static_cast<int32_t>(items0.size());
@@ -381,7 +417,7 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
         a.ng = de->ng_f;
         a.Yp = out->params;
         a.YS = out->S;
-        HIP_OR_FAIL(ctx, ens::launch_search(P, ctx->store_dtype, ctx->window, a, a.n_items, st));
+        seq.push_back({a, 0, a.n_items});
     } else {
         float *X = ctx->X.as<float>(), *XS = ctx->XS.as<float>();
         float *Y = ctx->Y.as<float>(), *YS = ctx->YS.as<float>();
@@ -399,15 +435,74 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
             a.YS = YS;
             for (int32_t k = 0; k < de->n_bucket && k < n_out; ++k) {
                 a.k = k;
-                HIP_OR_FAIL(ctx, ens::launch_search(P, ctx->store_dtype, ctx->window, a, a.n_items, st));
+                seq.push_back({a, s == 0 ? 0 : 1, a.n_items});
             }
             std::swap(X, Y);
             std::swap(XS, YS);
         }
-        HIP_OR_FAIL(ctx, hipMemcpyAsync(out->params, X, pbytes, hipMemcpyDeviceToDevice, st));
-        HIP_OR_FAIL(ctx, hipMemcpyAsync(out->S, XS, sbytes, hipMemcpyDeviceToDevice, st));
+        final_params = X;
+        final_S = XS;
     }
-    if (de->polish_steps > 0) {
+    ctx->stats = ens_stats{};
+    ctx->stats.struct_size = sizeof(ens_stats);
+    for (const auto &l : seq) ctx->stats.launches[l.kind] += 1;
+    const bool timing = ctx->tuning.collect_timing != 0;
+    const bool graph = ctx->tuning.use_graph != 0 && !timing;
+    if (timing) {
+        while (ctx->events.size() < 2 * seq.size()) {
+            hipEvent_t e;
+            HIP_OR_FAIL(ctx, hipEventCreate(&e));
+            ctx->events.push_back(e);
+        }
+    }
+    if (graph) {
+        bool same = ctx->graph_exec && ctx->graph_seq.size() == seq.size();
+        for (size_t i = 0; same && i < seq.size(); ++i)
+            same = std::memcmp(&seq[i], &ctx->graph_seq[i], sizeof(ens_ctx::Launch)) == 0;
+        if (!same) {
+            ctx->drop_graph();
+            HIP_OR_FAIL(ctx, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            hipError_t le = hipSuccess;
+            for (const auto &l : seq) {
+                le = ens::launch_search(P, ctx->store_dtype, ctx->window, l.kind, l.a, l.n_blocks, st);
+                if (le != hipSuccess) break;
+            }
+            hipGraph_t gph = nullptr;
+            hipError_t ce = hipStreamEndCapture(st, &gph);
+            HIP_OR_FAIL(ctx, le);
+            HIP_OR_FAIL(ctx, ce);
+            ctx->graph = gph;
+            HIP_OR_FAIL(ctx, hipGraphInstantiate(&ctx->graph_exec, gph, nullptr, nullptr, 0));
+            ctx->graph_seq = seq;
+        }
+        HIP_OR_FAIL(ctx, hipGraphLaunch(ctx->graph_exec, st));
+    } else {
+        for (size_t i = 0; i < seq.size(); ++i) {
+            const auto &l = seq[i];
+            if (timing) HIP_OR_FAIL(ctx, hipEventRecord(ctx->events[2 * i], st));
+            HIP_OR_FAIL(ctx, ens::launch_search(P, ctx->store_dtype, ctx->window, l.kind, l.a, l.n_blocks, st));
+            if (timing) HIP_OR_FAIL(ctx, hipEventRecord(ctx->events[2 * i + 1], st));
+        }
+    }
+    if (ens) {
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(out->params, final_params, pbytes, hipMemcpyDeviceToDevice, st));
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(out->S, final_S, sbytes, hipMemcpyDeviceToDevice, st));
+    }
+    hipEvent_t ev_p0 = nullptr, ev_p1 = nullptr, ev_r0 = nullptr, ev_r1 = nullptr;
+    if (timing) {
+        while (ctx->events.size() < 2 * seq.size() + 4) {
+            hipEvent_t e;
+            HIP_OR_FAIL(ctx, hipEventCreate(&e));
+            ctx->events.push_back(e);
+        }
+        ev_p0 = ctx->events[2 * seq.size()];
+        ev_p1 = ctx->events[2 * seq.size() + 1];
+        ev_r0 = ctx->events[2 * seq.size() + 2];
+        ev_r1 = ctx->events[2 * seq.size() + 3];
+    }
+    const bool polish = de->polish_steps > 0;
+    const bool rescore = de->rescore_fp64 && out->S64;
+    if (polish) {
         ens::PolishArgs pa{};
         pa.sv = view_of(ctx, false);
         pa.cmp_out = ctx->cmp_out.as<int32_t>();
@@ -422,19 +517,46 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
         pa.steps = de->polish_steps;
         pa.lr = de->polish_lr;
         pa.counters = ctx->counters.as<unsigned long long>();
+        if (timing) HIP_OR_FAIL(ctx, hipEventRecord(ev_p0, st));
         HIP_OR_FAIL(ctx, ens::launch_polish(P, ctx->store_dtype, ctx->window, pa, st));
+        if (timing) HIP_OR_FAIL(ctx, hipEventRecord(ev_p1, st));
+        ctx->stats.launches[2] = 1;
     } else if (out->S_pre_polish) {
         HIP_OR_FAIL(ctx, hipMemcpyAsync(out->S_pre_polish, out->S, sbytes, hipMemcpyDeviceToDevice, st));
     }
-    if (de->rescore_fp64 && out->S64) {
+    if (rescore) {
+        if (timing) HIP_OR_FAIL(ctx, hipEventRecord(ev_r0, st));
         HIP_OR_FAIL(ctx, ens::launch_eval64_grid(P, ctx->window, view_of(ctx, true), ctx->cmp_out.as<int32_t>(),
                                                  n_out, t_begin, n_t, out->params, out->S64, st));
+        if (timing) HIP_OR_FAIL(ctx, hipEventRecord(ev_r1, st));
+        ctx->stats.launches[3] = 1;
+        ctx->stats.evals[3] = n_s;
     }
-    unsigned long long cnt[4] = {0, 0, 0, 0};
+    unsigned long long cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     HIP_OR_FAIL(ctx, hipMemcpyAsync(cnt, ctx->counters.p, sizeof cnt, hipMemcpyDeviceToHost, st));
     HIP_OR_FAIL(ctx, hipStreamSynchronize(st));
-    out->n_evals = static_cast<int64_t>(cnt[0]);
-    out->sum_m = static_cast<int64_t>(cnt[1]);
+    for (int k = 0; k < 3; ++k) {
+        ctx->stats.evals[k] = static_cast<int64_t>(cnt[2 * k]);
+        ctx->stats.sum_m[k] = static_cast<int64_t>(cnt[2 * k + 1]);
+    }
+    if (timing) {
+        for (size_t i = 0; i < seq.size(); ++i) {
+            float ms = 0.f;
+            HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms, ctx->events[2 * i], ctx->events[2 * i + 1]));
+            ctx->stats.device_ms[seq[i].kind] += ms;
+        }
+        float ms = 0.f;
+        if (polish) {
+            HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms, ev_p0, ev_p1));
+            ctx->stats.device_ms[2] = ms;
+        }
+        if (rescore) {
+            HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms, ev_r0, ev_r1));
+            ctx->stats.device_ms[3] = ms;
+        }
+    }
+    out->n_evals = static_cast<int64_t>(cnt[0] + cnt[2]);
+    out->sum_m = static_cast<int64_t>(cnt[1] + cnt[3]);
     ctx->err.clear();
     return ENS_OK;
 }

@@ -347,7 +347,9 @@ __device__ __forceinline__ float eval_slices(const StoreView &sv, const Cand<flo
 // floor(64/NP) samples per wave, the trace loop split over nsl waves.  The
 // whole evolution (initial population and NG generations) runs in one
 // launch; with ENS, one launch is one trace step of a sweep in every bucket.
-template <int OP, int DT, int W>
+// KIND 0: exploration (plain evolution or ENS stage 0); KIND 1: ENS
+// exploitation stages.  KIND selects the counters and names the kernel.
+template <int OP, int DT, int W, int KIND>
 __global__ __launch_bounds__(512) void k_search(SearchArgs a)
 {
     extern __shared__ float lds[];
@@ -455,8 +457,8 @@ __global__ __launch_bounds__(512) void k_search(SearchArgs a)
         const uint64_t tot_ev = wave_sum(static_cast<uint64_t>(n_ev));
         const uint64_t tot_m = wave_sum(sum_m);
         if (lane == 0) {
-            atomicAdd(a.counters + 0, static_cast<unsigned long long>(tot_ev));
-            atomicAdd(a.counters + 1, static_cast<unsigned long long>(tot_m));
+            atomicAdd(a.counters + 2 * KIND, static_cast<unsigned long long>(tot_ev));
+            atomicAdd(a.counters + 2 * KIND + 1, static_cast<unsigned long long>(tot_m));
         }
     }
 }
@@ -490,6 +492,7 @@ __global__ __launch_bounds__(256) void k_polish(PolishArgs a)
     int64_t i_lo, i_hi;
     wave_trace_range(a.sv, j, ap, live, i_lo, i_hi);
     float b1k = 1.0f, b2k = 1.0f;
+    uint64_t sum_m = 0;
     for (int32_t k = 1; k <= a.steps; ++k) {
         float g[3];
         {
@@ -513,6 +516,7 @@ __global__ __launch_bounds__(256) void k_polish(PolishArgs a)
         acc.reset();
         accumulate_range<DT, W, float>(a.sv, cand, i_lo, i_hi, 0, 1, acc);
         const float Sn = finish_semblance(acc);
+        sum_m += live ? static_cast<uint64_t>(acc.M) : 0;
         if (Sn > best_S) {
             best_S = Sn;
 #pragma unroll
@@ -525,9 +529,10 @@ __global__ __launch_bounds__(256) void k_polish(PolishArgs a)
         a.S[c] = best_S;
     }
     const uint64_t n = wave_sum(static_cast<uint64_t>(live ? a.steps : 0));
+    const uint64_t msum = wave_sum(sum_m);
     if ((threadIdx.x & (WAVE - 1)) == 0) {
-        atomicAdd(a.counters + 2, static_cast<unsigned long long>(n));
-        atomicAdd(a.counters + 3, static_cast<unsigned long long>(n));
+        atomicAdd(a.counters + 4, static_cast<unsigned long long>(n));
+        atomicAdd(a.counters + 5, static_cast<unsigned long long>(msum));
     }
 }
 
@@ -672,14 +677,20 @@ hipError_t launch_backward(int op, int dtype, int window, const StoreView &sv, c
     return hipGetLastError();
 }
 
-hipError_t launch_search(int op, int dtype, int window, const SearchArgs &a, int32_t n_blocks,
-                         hipStream_t s)
+hipError_t launch_search(int op, int dtype, int window, int kind, const SearchArgs &a,
+                         int32_t n_blocks, hipStream_t s)
 {
     if (n_blocks == 0) return hipSuccess;
     const size_t lds = a.nsl > 1 ? sizeof(float) * 2 * a.nsl * (window + 2) * WAVE : 0;
-    ENS_DISPATCH_OP(op, ENS_DISPATCH_DT(dtype, ENS_DISPATCH_W(window,
-        hipLaunchKernelGGL((k_search<OP, DT, W>), dim3(static_cast<unsigned>(n_blocks)),
-                           dim3(WAVE * a.nsl), lds, s, a))));
+    if (kind == 0) {
+        ENS_DISPATCH_OP(op, ENS_DISPATCH_DT(dtype, ENS_DISPATCH_W(window,
+            hipLaunchKernelGGL((k_search<OP, DT, W, 0>), dim3(static_cast<unsigned>(n_blocks)),
+                               dim3(WAVE * a.nsl), lds, s, a))));
+    } else {
+        ENS_DISPATCH_OP(op, ENS_DISPATCH_DT(dtype, ENS_DISPATCH_W(window,
+            hipLaunchKernelGGL((k_search<OP, DT, W, 1>), dim3(static_cast<unsigned>(n_blocks)),
+                               dim3(WAVE * a.nsl), lds, s, a))));
+    }
     return hipGetLastError();
 }
 

@@ -43,7 +43,7 @@ struct SearchArgs {
     uint64_t cr_thr;          // crossover draw threshold ceil(CR 2^32)
     const float *Xp, *XS;     // previous stage state [n_out][n_t][P], [n_out][n_t]
     float *Yp, *YS;           // this stage's state
-    unsigned long long *counters;  // [0] evaluations, [1] participating traces
+    unsigned long long *counters;  // [2 KIND] evaluations, [2 KIND + 1] participating traces
 };
 
 struct PolishArgs {
@@ -56,7 +56,7 @@ struct PolishArgs {
     float *S_pre;             // optional copy of the incoming S
     int32_t steps;
     float lr;
-    unsigned long long *counters;  // [2] forward evaluations, [3] adjoint passes
+    unsigned long long *counters;  // [4] forward evaluations, [5] participating traces
 };
 
 // launch wrappers (return hipSuccess or the launch error)
@@ -74,8 +74,8 @@ hipError_t launch_eval64_grid(int op, int window, const StoreView &sv_f32, const
                               double *S, hipStream_t s);
 hipError_t launch_backward(int op, int dtype, int window, const StoreView &sv, const CandView &cv,
                            const float *dS, float *g, hipStream_t s);
-hipError_t launch_search(int op, int dtype, int window, const SearchArgs &a, int32_t n_blocks,
-                         hipStream_t s);
+hipError_t launch_search(int op, int dtype, int window, int kind, const SearchArgs &a,
+                         int32_t n_blocks, hipStream_t s);
 hipError_t launch_polish(int op, int dtype, int window, const PolishArgs &a, hipStream_t s);
 hipError_t launch_philox(int64_t n, const uint64_t *ctr, const uint64_t *key, uint64_t *out,
                          hipStream_t s);

@@ -105,6 +105,10 @@ def test_tuning_and_building_block_validation():
         assert lib.ens_set_tuning(h, C.byref(t)) == -2
         t.waves_per_sample_group = 4
         assert lib.ens_set_tuning(h, C.byref(t)) == 0
+        t.use_graph, t.collect_timing = 1, 1
+        assert lib.ens_set_tuning(h, C.byref(t)) == -1
+        st = ens._sized(ens.Stats)
+        assert lib.ens_last_stats(h, C.byref(st)) == 0 and st.launches[0] == 0
         assert lib.ens_de_trial(h, 1, 3, 3, 1, 1, 1, 0.5, 0.9, 1, 1, 1) == -2   # np < 4
         assert lib.ens_de_trial(h, 1, 8, 2, 1, 1, 1, 0.5, 0.9, 1, 1, 1) == -1   # P = 2
         assert lib.ens_de_trial(h, 1, 8, 3, 1, 1, 1, 0.5, 1.5, 1, 1, 1) == -2   # CR > 1
