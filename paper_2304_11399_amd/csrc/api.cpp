@@ -216,6 +216,7 @@ ens_status ens_bind(ens_ctx *ctx, const ens_traces *tr, const ens_geometry *g, c
     if (tr->n_traces < 1 || tr->nt < 2 || tr->ld < tr->nt)
         return fail(ctx, ENS_E_INVALID, "ens_bind: need n_traces >= 1, nt >= 2, ld >= nt");
     if (tr->nt > (1 << 20)) return fail(ctx, ENS_E_RANGE, "ens_bind: nt too large");
+    if (tr->n_traces >= (int64_t(1) << 31)) return fail(ctx, ENS_E_RANGE, "ens_bind: too many traces");
     if (!(tr->dt > 0.f) || !finite(tr->dt) || !(g->dx > 0.f) || !finite(g->dx))
         return fail(ctx, ENS_E_RANGE, "ens_bind: dt and dx must be positive");
     if (tr->store_dtype < ENS_DTYPE_F32 || tr->store_dtype > ENS_DTYPE_BF16)

@@ -4,7 +4,8 @@
 //  - Trace store layout: each trace row holds PAD zero samples, the nt
 //    samples, then zeros up to the row stride, so a window read around any
 //    participating traveltime stays inside the row and reads 0 outside the
-//    record without a bounds test.
+//    record without a bounds test; a trace that does not take part reads its
+//    window from the leading zeros, which contributes nothing.
 //  - accum_trace(): traveltime of one (candidate, trace) pair, linear
 //    interpolation of the W+1 samples around it and accumulation of the
 //    window sums s_k and the energy E (section "Traveltime parameter search":
@@ -21,7 +22,7 @@
 
 namespace ens {
 
-constexpr int PAD = 8;     // zero samples before and after each stored trace
+constexpr int PAD = 16;    // zero samples before and after each stored trace (> W)
 constexpr int WAVE = 64;
 
 // ---------------------------------------------------------------------------
@@ -157,72 +158,93 @@ struct Acc {
     }
 };
 
+// Fused multiply-add in the operands' own precision.
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float floor_r(float x) { return __builtin_floorf(x); }
+__device__ __forceinline__ double floor_r(double x) { return __builtin_floor(x); }
+// Clamp into [-1e30, 1e30] (keeps the fraction of a far-off traveltime finite).
+__device__ __forceinline__ float clamp_big(float x) { return __builtin_amdgcn_fmed3f(x, -1e30f, 1e30f); }
+__device__ __forceinline__ double clamp_big(double x) { return __builtin_fmin(__builtin_fmax(x, -1e30), 1e30); }
+
 __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double fast_sqrt(double x) { return __builtin_sqrt(x); }
 __device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
 
-// Traveltime of (candidate, trace): participation flag, sample index n and
-// fraction f.  q < 0, dtau out of range, or the trace's CMP outside the
-// candidate's aperture: not participating.
+// Per-CMP part of the moveout for one candidate: al dm + be dm^2 with
+// dm = (c - j) dx, and whether the CMP lies inside the candidate's aperture.
 template <typename R>
-struct TT {
-    bool ok;
-    int32_t n;
-    R f;
-    R tau_abs;    // sqrt(q) in samples (for the adjoint)
-    R dm;         // midpoint displacement (m)
+struct CmpTerm {
+    R part;
+    R dm;
+    bool in_ap;
 };
 
 template <typename R>
-__device__ __forceinline__ TT<R> traveltime(const Cand<R> &c, const TraceMeta &tm)
+__device__ __forceinline__ CmpTerm<R> cmp_term(const Cand<R> &cand, int32_t c, R dx)
+{
+    CmpTerm<R> t;
+    const int32_t dc = c - cand.j;
+    t.dm = static_cast<R>(dc) * dx;
+    t.part = fmadd(cand.be, t.dm * t.dm, cand.al * t.dm);
+    t.in_ap = dc <= cand.ap && -dc <= cand.ap;
+    return t;
+}
+
+// Traveltime of (candidate, trace) in sample units.  q = n0^2 + mo < 0 gives
+// dtau < -n0 (tau clamps to 0, dtau = mo / n0) and so fails the range test,
+// as does any trace outside the candidate's aperture.  off: column of the
+// window's first sample in the padded row, or 0 (a run of zero padding) for
+// a trace that does not take part.
+template <typename R>
+struct TT {
+    bool ok;
+    uint32_t off;
+    R f;
+    R tau;        // sqrt(q) in samples
+};
+
+template <int W, typename R>
+__device__ __forceinline__ TT<R> traveltime(const Cand<R> &c, const CmpTerm<R> &ct, R h2)
 {
     TT<R> r;
-    const R dm = static_cast<R>(tm.cx) - c.jx;
-    const R dm2 = dm * dm;
-    R h2;
-    if constexpr (sizeof(R) == 8) {
-        h2 = static_cast<R>(tm.h) * static_cast<R>(tm.h);
-    } else {
-        h2 = tm.h2;
-    }
-    const R mo = __builtin_fma(c.ga, h2, __builtin_fma(c.be, dm2, c.al * dm));
+    const R mo = fmadd(c.ga, h2, ct.part);
     const R q = c.n0sq + mo;
     const R tau = fast_sqrt(q > R(0) ? q : R(0));
-    const R den = tau + c.n0f;
-    const R dtau = den > R(0) ? mo * fast_rcp(den) : R(0);
-    const int32_t dc = tm.cmp - c.j;
-    const bool in_ap = dc <= c.ap && -dc <= c.ap;
-    r.ok = in_ap && (q >= R(0)) && (dtau >= c.lo_lim) && (dtau <= c.hi_lim);
-    const R fl = __builtin_floor(dtau);
+    const R s = tau + c.n0f;
+    const R den = s > R(1e-30) ? s : R(1e-30);
+    const R dtau = clamp_big(mo * fast_rcp(den));
+    r.ok = ct.in_ap && (dtau >= c.lo_lim) && (dtau <= c.hi_lim);
+    const R fl = floor_r(dtau);
     r.f = dtau - fl;
-    r.n = r.ok ? c.n0 + static_cast<int32_t>(fl) : 0;
-    r.tau_abs = tau;
-    r.dm = dm;
+    const int32_t col = c.n0 + static_cast<int32_t>(fl) + (PAD - W / 2);
+    r.off = r.ok ? static_cast<uint32_t>(col) : 0u;
+    r.tau = tau;
     return r;
 }
 
-// Accumulate one trace into the window sums.  row: the trace's sample 0.
+// Accumulate one trace into the window sums.  row: the padded trace row.
 template <int DT, int W, bool SCALED, typename R>
-__device__ __forceinline__ void accum_trace(Acc<W, R> &acc, const Cand<R> &c, const TraceMeta &tm,
-                                            const typename Store<DT>::T *__restrict__ row,
+__device__ __forceinline__ void accum_trace(Acc<W, R> &acc, const Cand<R> &c, const CmpTerm<R> &ct,
+                                            R h2, const typename Store<DT>::T *__restrict__ row,
                                             float scale)
 {
-    const TT<R> tt = traveltime(c, tm);
-    R wb = tt.ok ? tt.f : R(0);
-    R wa = tt.ok ? R(1) - tt.f : R(0);
+    const TT<R> tt = traveltime<W>(c, ct, h2);
+    R wb = tt.f;
+    R wa = R(1) - tt.f;
     if constexpr (SCALED) {
         wa *= static_cast<R>(scale);
         wb *= static_cast<R>(scale);
     }
     acc.M += tt.ok ? 1 : 0;
     float u[W + 1];
-    load_window<DT, W + 1>(row + (tt.n - W / 2), u);
+    load_window<DT, W + 1>(row + tt.off, u);
 #pragma unroll
     for (int k = 0; k < W; ++k) {
-        const R a = __builtin_fma(wb, static_cast<R>(u[k + 1]), wa * static_cast<R>(u[k]));
+        const R a = fmadd(wb, static_cast<R>(u[k + 1]), wa * static_cast<R>(u[k]));
         acc.s[k] += a;
-        acc.E = __builtin_fma(a, a, acc.E);
+        acc.E = fmadd(a, a, acc.E);
     }
 }
 
@@ -231,7 +253,7 @@ __device__ __forceinline__ R finish_semblance(const Acc<W, R> &acc)
 {
     R N = R(0);
 #pragma unroll
-    for (int k = 0; k < W; ++k) N = __builtin_fma(acc.s[k], acc.s[k], N);
+    for (int k = 0; k < W; ++k) N = fmadd(acc.s[k], acc.s[k], N);
     if (acc.M > 0 && acc.E > R(0)) return N / (static_cast<R>(acc.M) * acc.E);
     return R(0);
 }

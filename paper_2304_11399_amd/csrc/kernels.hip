@@ -92,42 +92,69 @@ __device__ __forceinline__ T wave_sum(T v)
     return v;
 }
 
-// Union of the lanes' aperture trace ranges (wave-uniform result).
-__device__ __forceinline__ void wave_trace_range(const StoreView &sv, int32_t j, int32_t ap, bool live,
-                                                 int64_t &i_lo, int64_t &i_hi)
+// Union of the lanes' aperture CMP ranges (wave-uniform; empty: c_hi < c_lo).
+__device__ __forceinline__ void wave_cmp_range(const StoreView &sv, int32_t j, int32_t ap, bool live,
+                                               int32_t &c_lo, int32_t &c_hi)
 {
-    int32_t c_lo = j - ap < 0 ? 0 : j - ap;
-    int32_t c_hi = j + ap > sv.n_cmp - 1 ? sv.n_cmp - 1 : j + ap;
+    int32_t lo = j - ap < 0 ? 0 : j - ap;
+    int32_t hi = j + ap > sv.n_cmp - 1 ? sv.n_cmp - 1 : j + ap;
     if (!live) {
-        c_lo = 0x7fffffff;
-        c_hi = -1;
+        lo = 0x7fffffff;
+        hi = -1;
     }
-    c_lo = __builtin_amdgcn_readfirstlane(wave_min(c_lo));
-    c_hi = __builtin_amdgcn_readfirstlane(wave_max(c_hi));
-    if (c_hi < c_lo) {
-        i_lo = i_hi = 0;
-        return;
-    }
-    i_lo = sv.cmp_ptr[c_lo];
-    i_hi = sv.cmp_ptr[c_hi + 1];
+    c_lo = __builtin_amdgcn_readfirstlane(wave_min(lo));
+    c_hi = __builtin_amdgcn_readfirstlane(wave_max(hi));
 }
 
-// Window sums of one candidate over traces [i_lo, i_hi) with stride `step`
-// starting at i_lo + first.
-template <int DT, int W, typename R>
-__device__ __forceinline__ void accumulate_range(const StoreView &sv, const Cand<R> &cand,
-                                                 int64_t i_lo, int64_t i_hi, int32_t first,
-                                                 int32_t step, Acc<W, R> &acc)
+template <typename R>
+__device__ __forceinline__ R h2_of(const TraceMeta &tm)
+{
+    if constexpr (sizeof(R) == 8)
+        return static_cast<R>(tm.h) * static_cast<R>(tm.h);
+    else
+        return tm.h2;
+}
+
+// Window sums of one candidate over the traces of CMPs c_lo..c_hi; in each
+// CMP the traces first, first + step, first + 2 step, ... (two per step of
+// the loop, so that their gathers are in flight together).
+template <int DT, int W, bool SCALED, typename R>
+__device__ __forceinline__ void accumulate_cmps(const StoreView &sv, const Cand<R> &cand, int32_t c_lo,
+                                                int32_t c_hi, int32_t first, int32_t step,
+                                                Acc<W, R> &acc)
 {
     using T = typename Store<DT>::T;
     const T *store = static_cast<const T *>(sv.store);
-    if (sv.scale) {
-        for (int64_t i = i_lo + first; i < i_hi; i += step)
-            accum_trace<DT, W, true>(acc, cand, sv.meta[i], store + i * sv.ld + PAD, sv.scale[i]);
-    } else {
-        for (int64_t i = i_lo + first; i < i_hi; i += step)
-            accum_trace<DT, W, false>(acc, cand, sv.meta[i], store + i * sv.ld + PAD, 1.0f);
+    const R dx = static_cast<R>(sv.dx);
+    for (int32_t c = c_lo; c <= c_hi; ++c) {
+        const CmpTerm<R> ct = cmp_term(cand, c, dx);
+        const int32_t i1 = static_cast<int32_t>(sv.cmp_ptr[c + 1]);
+        int32_t i = static_cast<int32_t>(sv.cmp_ptr[c]) + first;
+        for (; i + step < i1; i += 2 * step) {
+            const int32_t i2 = i + step;
+            accum_trace<DT, W, SCALED>(acc, cand, ct, h2_of<R>(sv.meta[i]),
+                                       store + static_cast<size_t>(i) * sv.ld,
+                                       SCALED ? sv.scale[i] : 1.0f);
+            accum_trace<DT, W, SCALED>(acc, cand, ct, h2_of<R>(sv.meta[i2]),
+                                       store + static_cast<size_t>(i2) * sv.ld,
+                                       SCALED ? sv.scale[i2] : 1.0f);
+        }
+        if (i < i1)
+            accum_trace<DT, W, SCALED>(acc, cand, ct, h2_of<R>(sv.meta[i]),
+                                       store + static_cast<size_t>(i) * sv.ld,
+                                       SCALED ? sv.scale[i] : 1.0f);
     }
+}
+
+template <int DT, int W, typename R>
+__device__ __forceinline__ void accumulate_range(const StoreView &sv, const Cand<R> &cand, int32_t c_lo,
+                                                 int32_t c_hi, int32_t first, int32_t step,
+                                                 Acc<W, R> &acc)
+{
+    if (sv.scale)
+        accumulate_cmps<DT, W, true, R>(sv, cand, c_lo, c_hi, first, step, acc);
+    else
+        accumulate_cmps<DT, W, false, R>(sv, cand, c_lo, c_hi, first, step, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -147,11 +174,11 @@ __global__ __launch_bounds__(256) void k_eval(StoreView sv, CandView cv, R *__re
     for (int d = 0; d < OP; ++d) p[d] = static_cast<R>(cv.params[cc * OP + d]);
     const Cand<R> cand = make_cand<OP, R>(p, n0, j, ap, sv.nt, static_cast<R>(sv.dt),
                                           static_cast<R>(sv.dx));
-    int64_t i_lo, i_hi;
-    wave_trace_range(sv, j, ap, live, i_lo, i_hi);
+    int32_t c_lo, c_hi;
+    wave_cmp_range(sv, j, ap, live, c_lo, c_hi);
     Acc<W, R> acc;
     acc.reset();
-    accumulate_range<DT, W, R>(sv, cand, i_lo, i_hi, 0, 1, acc);
+    accumulate_range<DT, W, R>(sv, cand, c_lo, c_hi, 0, 1, acc);
     if (live) {
         S_out[c] = finish_semblance(acc);
         if (M_out) M_out[c] = acc.M;
@@ -178,11 +205,11 @@ __global__ __launch_bounds__(256) void k_eval64_grid(StoreView sv, const int32_t
     for (int d = 0; d < OP; ++d) p[d] = static_cast<double>(params[cc * OP + d]);
     const Cand<double> cand = make_cand<OP, double>(p, n0, j, ap, sv.nt, static_cast<double>(sv.dt),
                                                     static_cast<double>(sv.dx));
-    int64_t i_lo, i_hi;
-    wave_trace_range(sv, j, ap, live, i_lo, i_hi);
+    int32_t c_lo, c_hi;
+    wave_cmp_range(sv, j, ap, live, c_lo, c_hi);
     Acc<W, double> acc;
     acc.reset();
-    accumulate_range<DT_F32, W, double>(sv, cand, i_lo, i_hi, 0, 1, acc);
+    accumulate_range<DT_F32, W, double>(sv, cand, c_lo, c_hi, 0, 1, acc);
     if (live) S_out[c] = finish_semblance(acc);
 }
 
@@ -194,13 +221,13 @@ __global__ __launch_bounds__(256) void k_eval64_grid(StoreView sv, const int32_t
 
 template <int OP, int DT, int W>
 __device__ __forceinline__ float semblance_grad_lane(const StoreView &sv, const Cand<float> &cand,
-                                                     int64_t i_lo, int64_t i_hi, float *g)
+                                                     int32_t c_lo, int32_t c_hi, float *g)
 {
     using T = typename Store<DT>::T;
     const T *store = static_cast<const T *>(sv.store);
     Acc<W, float> acc;
     acc.reset();
-    accumulate_range<DT, W, float>(sv, cand, i_lo, i_hi, 0, 1, acc);
+    accumulate_range<DT, W, float>(sv, cand, c_lo, c_hi, 0, 1, acc);
     const float S = finish_semblance(acc);
 #pragma unroll
     for (int d = 0; d < OP; ++d) g[d] = 0.0f;
@@ -208,28 +235,32 @@ __device__ __forceinline__ float semblance_grad_lane(const StoreView &sv, const 
     const float coef = nonzero ? 2.0f / (static_cast<float>(acc.M) * acc.E) : 0.0f;
     const float MS = static_cast<float>(acc.M) * S;
     const float inv_dt = 1.0f / sv.dt;
-    for (int64_t i = i_lo; i < i_hi; ++i) {
-        const TraceMeta tm = sv.meta[i];
-        const TT<float> tt = traveltime(cand, tm);
-        const bool use = nonzero && tt.ok && tt.tau_abs > 0.0f;
-        const float sc = sv.scale ? sv.scale[i] : 1.0f;
-        float u[W + 1];
-        load_window<DT, W + 1>(store + i * sv.ld + PAD + (tt.n - W / 2), u);
-        const float wa = (1.0f - tt.f) * sc, wb = tt.f * sc;
-        float dSdtau = 0.0f;
+    for (int32_t c = c_lo; c <= c_hi; ++c) {
+        const CmpTerm<float> ct = cmp_term(cand, c, sv.dx);
+        const int32_t i1 = static_cast<int32_t>(sv.cmp_ptr[c + 1]);
+        for (int32_t i = static_cast<int32_t>(sv.cmp_ptr[c]); i < i1; ++i) {
+            const float h2 = sv.meta[i].h2;
+            const TT<float> tt = traveltime<W>(cand, ct, h2);
+            const bool use = nonzero && tt.ok && tt.tau > 0.0f;
+            const float sc = sv.scale ? sv.scale[i] : 1.0f;
+            float u[W + 1];
+            load_window<DT, W + 1>(store + static_cast<size_t>(i) * sv.ld + tt.off, u);
+            const float wa = (1.0f - tt.f) * sc, wb = tt.f * sc;
+            float dSdtau = 0.0f;
 #pragma unroll
-        for (int k = 0; k < W; ++k) {
-            const float a = __builtin_fmaf(wb, u[k + 1], wa * u[k]);
-            dSdtau = __builtin_fmaf(acc.s[k] - MS * a, (u[k + 1] - u[k]) * sc, dSdtau);
-        }
-        const float r = use ? coef * dSdtau / (2.0f * tt.tau_abs) : 0.0f;
-        if constexpr (OP == 1) {
-            g[0] += r * tm.h2 * inv_dt * inv_dt;
-        } else {
-            const float dm = tt.dm;
-            g[0] += r * 2.0f * (cand.n0f + cand.As * dm) * dm * inv_dt;
-            g[1] += r * cand.n0f * dm * dm * inv_dt;
-            g[2] += r * cand.n0f * tm.h2 * inv_dt;
+            for (int k = 0; k < W; ++k) {
+                const float a = __builtin_fmaf(wb, u[k + 1], wa * u[k]);
+                dSdtau = __builtin_fmaf(acc.s[k] - MS * a, (u[k + 1] - u[k]) * sc, dSdtau);
+            }
+            const float r = use ? coef * dSdtau / (2.0f * tt.tau) : 0.0f;
+            if constexpr (OP == 1) {
+                g[0] += r * h2 * inv_dt * inv_dt;
+            } else {
+                const float dm = ct.dm;
+                g[0] += r * 2.0f * (cand.n0f + cand.As * dm) * dm * inv_dt;
+                g[1] += r * cand.n0f * dm * dm * inv_dt;
+                g[2] += r * cand.n0f * h2 * inv_dt;
+            }
         }
     }
     return S;
@@ -248,10 +279,10 @@ __global__ __launch_bounds__(256) void k_backward(StoreView sv, CandView cv, con
 #pragma unroll
     for (int d = 0; d < OP; ++d) p[d] = cv.params[cc * OP + d];
     const Cand<float> cand = make_cand<OP, float>(p, n0, j, ap, sv.nt, sv.dt, sv.dx);
-    int64_t i_lo, i_hi;
-    wave_trace_range(sv, j, ap, live, i_lo, i_hi);
+    int32_t c_lo, c_hi;
+    wave_cmp_range(sv, j, ap, live, c_lo, c_hi);
     float g[3];
-    semblance_grad_lane<OP, DT, W>(sv, cand, i_lo, i_hi, g);
+    semblance_grad_lane<OP, DT, W>(sv, cand, c_lo, c_hi, g);
     if (live) {
         const float ds = dS[c];
 #pragma unroll
@@ -312,16 +343,17 @@ __device__ __forceinline__ void load_clamped(const float *__restrict__ src, cons
 }
 
 // Semblance of each lane's candidate, the trace loop split over the
-// workgroup's nsl waves (wave w takes traces i_lo + w, i_lo + w + nsl, ...);
+// workgroup's nsl waves (in every CMP, wave w takes the CMP's traces w,
+// w + nsl, w + 2 nsl, ...);
 // partial sums meet in LDS and every wave adds them in the same order.
 template <int DT, int W>
-__device__ __forceinline__ float eval_slices(const StoreView &sv, const Cand<float> &cand, int64_t i_lo,
-                                             int64_t i_hi, int32_t wave, int32_t nsl, int32_t lane,
+__device__ __forceinline__ float eval_slices(const StoreView &sv, const Cand<float> &cand, int32_t c_lo,
+                                             int32_t c_hi, int32_t wave, int32_t nsl, int32_t lane,
                                              float *lds, int &buf, int32_t &M)
 {
     Acc<W, float> acc;
     acc.reset();
-    accumulate_range<DT, W, float>(sv, cand, i_lo, i_hi, wave, nsl, acc);
+    accumulate_range<DT, W, float>(sv, cand, c_lo, c_hi, wave, nsl, acc);
     if (nsl > 1) {
         float *mine = lds + ((buf * nsl + wave) * (W + 2)) * WAVE + lane;
 #pragma unroll
@@ -385,7 +417,6 @@ __global__ __launch_bounds__(512) void k_search(SearchArgs a)
     // apertures grow or shrink linearly in t: the item's extreme samples bound them
     const int32_t amax = max(a.sv.ap_tab[t_start], a.sv.ap_tab[t_start + ns - 1]);
     const int32_t c_lo = max(0, j - amax), c_hi = min(a.sv.n_cmp - 1, j + amax);
-    const int64_t i_lo = a.sv.cmp_ptr[c_lo], i_hi = a.sv.cmp_ptr[c_hi + 1];
     const uint64_t sid = static_cast<uint64_t>(n0) + static_cast<uint64_t>(a.sv.nt) * static_cast<uint64_t>(j);
     const uint64_t stage = static_cast<uint64_t>(a.stage);
 
@@ -420,7 +451,7 @@ __global__ __launch_bounds__(512) void k_search(SearchArgs a)
     uint64_t sum_m = 0;
     {
         const Cand<float> cand = make_cand<OP, float>(x, n0, j, ap, a.sv.nt, a.sv.dt, a.sv.dx);
-        const float Sev = eval_slices<DT, W>(a.sv, cand, i_lo, i_hi, wave, nsl, lane, lds, buf, M);
+        const float Sev = eval_slices<DT, W>(a.sv, cand, c_lo, c_hi, wave, nsl, lane, lds, buf, M);
         if (!scored) {
             S = Sev;
             if (live) {
@@ -435,7 +466,7 @@ __global__ __launch_bounds__(512) void k_search(SearchArgs a)
         float u[3] = {0.f, 0.f, 0.f};
         make_trial<OP>(x, S, base, np, slot, w, a.F, a.cr_thr, lo, hi, u);
         const Cand<float> cand = make_cand<OP, float>(u, n0, j, ap, a.sv.nt, a.sv.dt, a.sv.dx);
-        const float St = eval_slices<DT, W>(a.sv, cand, i_lo, i_hi, wave, nsl, lane, lds, buf, M);
+        const float St = eval_slices<DT, W>(a.sv, cand, c_lo, c_hi, wave, nsl, lane, lds, buf, M);
         if (live) {
             n_ev += 1;
             sum_m += static_cast<uint64_t>(M);
@@ -489,15 +520,15 @@ __global__ __launch_bounds__(256) void k_polish(PolishArgs a)
     }
     float best_S = a.S[cc];
     if (live && a.S_pre) a.S_pre[c] = best_S;
-    int64_t i_lo, i_hi;
-    wave_trace_range(a.sv, j, ap, live, i_lo, i_hi);
+    int32_t c_lo, c_hi;
+    wave_cmp_range(a.sv, j, ap, live, c_lo, c_hi);
     float b1k = 1.0f, b2k = 1.0f;
     uint64_t sum_m = 0;
     for (int32_t k = 1; k <= a.steps; ++k) {
         float g[3];
         {
             const Cand<float> cand = make_cand<OP, float>(p, n0, j, ap, a.sv.nt, a.sv.dt, a.sv.dx);
-            semblance_grad_lane<OP, DT, W>(a.sv, cand, i_lo, i_hi, g);
+            semblance_grad_lane<OP, DT, W>(a.sv, cand, c_lo, c_hi, g);
         }
         b1k *= 0.9f;
         b2k *= 0.999f;
@@ -514,7 +545,7 @@ __global__ __launch_bounds__(256) void k_polish(PolishArgs a)
         const Cand<float> cand = make_cand<OP, float>(p, n0, j, ap, a.sv.nt, a.sv.dt, a.sv.dx);
         Acc<W, float> acc;
         acc.reset();
-        accumulate_range<DT, W, float>(a.sv, cand, i_lo, i_hi, 0, 1, acc);
+        accumulate_range<DT, W, float>(a.sv, cand, c_lo, c_hi, 0, 1, acc);
         const float Sn = finish_semblance(acc);
         sum_m += live ? static_cast<uint64_t>(acc.M) : 0;
         if (Sn > best_S) {
