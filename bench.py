@@ -38,6 +38,22 @@ def flops_per_pair(op, window):
     return tt + 6 * window + 1
 
 
+def measured_traffic(workload):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    counter summary, or None when the kernel sources changed since then."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in ("device.h", "kernels.hip"):
+        h.update(open(os.path.join(ROOT, "paper_2304_11399_amd", "csrc", f), "rb").read())
+    if h.hexdigest() != rec["source_sha256"]:
+        return None
+    return rec
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,8 +176,14 @@ def main():
     flops_per_launch = ex["sum_m"] * flops_per_pair(wl["op"], W) / ex["launches"]
     gbs = bytes_per_launch / per_launch_s / 1e9
     tflops = flops_per_launch / per_launch_s / 1e12
+    prof = measured_traffic(args.workload)
+    traffic = None
+    if prof is not None and prof["kernel"].startswith(f"void ens::k_search<{wl['op']}, "):
+        traffic = round(prof["traffic_bytes_per_launch"])
     roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": FP32_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(tflops / FP32_PEAK_TFLOPS, 4), "traffic": None,
+            "unit": "TFLOP/s", "frac": round(tflops / FP32_PEAK_TFLOPS, 4), "traffic": traffic,
+            "flops_per_pair": flops_per_pair(wl["op"], W),
+            "algorithmic_bytes_per_launch": round(bytes_per_launch),
             "kernel": f"k_search<{wl['op']},{ {'f32': 0, 'f16': 1, 'bf16': 2}[store]},{W},0>",
             "launches": ex["launches"], "avg_launch_ms": round(ex["device_ms"] / ex["launches"], 4),
             "algorithmic_gather": {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
