@@ -62,7 +62,13 @@ def parse():
     ap.add_argument("--workload", default="crs_ens")
     ap.add_argument("--store", default=None, help="f32, f16 or bf16 (default: the workload's)")
     ap.add_argument("--waves", type=int, default=0, help="trace slices per population (0: auto)")
+    ap.add_argument("--order", type=int, default=0,
+                    help="work-item order: 1 XCD-contiguous, 2 costliest first (0: measure)")
+    ap.add_argument("--occupancy", type=int, default=0,
+                    help="search kernel registers: 1 as compiled, 2 held to 64 (0: measure)")
     ap.add_argument("--graph", action="store_true", help="replay the trace steps as a HIP graph")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the equal-accuracy comparison of ENS with plain per-sample DE")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gap", action="store_true")
     return ap.parse_args()
@@ -81,18 +87,65 @@ def cpu_baseline(g, wl, de, bounds):
         de_s = dict(de, n_bucket=4)
         what = f"ENS over CMPs {cmp_out[0]}..{cmp_out[-1]} (one 4-CMP bucket) x t {t0}..{t1 - 1}"
     else:
-        cmp_out = np.arange(0, min(4, g.n_cmp), dtype=np.int32)
+        cmp_out = np.arange(g.n_cmp, dtype=np.int32)
         t0, t1 = 0, g.nt
         de_s = de
-        what = f"plain DE over CMPs 0..{cmp_out[-1]} x all t"
+        what = "plain DE over the whole line, repeated for at least 10 s"
     start = time.perf_counter()
-    _, _, ev = L.search(bounds, de_s, wl["search_seed"], cmp_out=cmp_out, t_begin=t0, t_end=t1)
+    n = ev = 0
+    while True:
+        _, _, e = L.search(bounds, de_s, wl["search_seed"], cmp_out=cmp_out, t_begin=t0, t_end=t1)
+        n += cmp_out.size * (t1 - t0)
+        ev += e
+        if wl["de"]["ens_enabled"] or time.perf_counter() - start >= 10.0:
+            break
     sec = time.perf_counter() - start
-    n = cmp_out.size * (t1 - t0)
     threads = oracle.lib().or_num_threads()
     return {"value": round(n / sec, 3), "unit": "ZO samples/s", "cores": int(threads),
             "kind": "oracle", "sample": f"{what}: {n} ZO samples, {ev} evaluations, "
             f"{sec:.1f} s, {ev / sec:.4g} evals/s"}
+
+
+def compare_equal_accuracy(ctx, bounds, wl, store, g, run_main):
+    """ENS against the per-sample search the paper compares with, each over a
+    few budgets: the fastest budget whose mean gap to the reference maxima is
+    <= 1e-3 is each method's throughput at that accuracy."""
+    import torch
+    de0 = dict(wl["de"])
+    rows = []
+    variants = [("ens", dict(de0)),
+                ("ens", dict(de0, np_lo=16, np_hi=16, ng_f=20)),
+                ("ens", dict(de0, np_lo=16, np_hi=16, ng_f=10)),
+                ("ens", dict(de0, np_lo=8, np_hi=8, ng_f=8)),
+                ("plain", dict(de0, ens_enabled=0, np_lo=16, np_hi=16, ng_f=20)),
+                ("plain", dict(de0, ens_enabled=0, ng_f=40)),
+                ("plain", dict(de0, ens_enabled=0)),
+                ("plain", dict(de0, ens_enabled=0, ng_f=160))]
+    if not wl["de"]["ens_enabled"]:
+        return None
+    for kind, de in variants:
+        run_main(de)  # measures the launch shape once, outside the clock
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = run_main(de)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        gap = gap_stats(wl["name"], out["S64"].cpu().numpy(), g.nt, g)
+        rows.append({"method": kind, "np": de["np_lo"], "ng": de["ng_f"],
+                     "ms": round(1e3 * sec, 2), "zo_samples_per_s": round(g.n_cmp * g.nt / sec, 1),
+                     "evals": out["n_evals"], "gap_mean": gap["mean"] if gap else None,
+                     "frac_le_1e-3": gap["frac_le_1e-3"] if gap else None})
+    best = {}
+    for r in rows:
+        if r["gap_mean"] is not None and r["gap_mean"] <= 1e-3:
+            b = best.get(r["method"])
+            if b is None or r["zo_samples_per_s"] > b["zo_samples_per_s"]:
+                best[r["method"]] = r
+    speedup = None
+    if "ens" in best and "plain" in best:
+        speedup = round(best["ens"]["zo_samples_per_s"] / best["plain"]["zo_samples_per_s"], 3)
+    return {"store": store, "runs": rows, "best_at_gap_le_1e-3": best,
+            "ens_over_plain_zo_samples_per_s": speedup}
 
 
 def gap_stats(name, S64, nt, g):
@@ -133,7 +186,8 @@ def main():
     stream = torch.cuda.Stream() if args.graph else torch.cuda.current_stream()
     with torch.cuda.stream(stream):
         ctx = ens.Context(stream)
-        ctx.set_tuning(waves_per_sample_group=args.waves, use_graph=int(args.graph))
+        ctx.set_tuning(waves_per_sample_group=args.waves, use_graph=int(args.graph),
+                       item_order=args.order, occupancy=args.occupancy)
         traces = torch.from_numpy(g.traces).cuda()
         P_d = g.n_cmp * g.nt
 
@@ -155,10 +209,17 @@ def main():
         S64 = out["S64"].cpu().numpy()
 
         # one more step with per-launch event timing, outside the timed region
-        ctx.set_tuning(waves_per_sample_group=args.waves, collect_timing=1)
+        ctx.set_tuning(waves_per_sample_group=args.waves, collect_timing=1, item_order=args.order,
+                       occupancy=args.occupancy)
         step()
         st = ctx.stats()
-        ctx.set_tuning(waves_per_sample_group=args.waves, use_graph=int(args.graph))
+        ctx.set_tuning(waves_per_sample_group=args.waves, item_order=args.order,
+                       occupancy=args.occupancy)
+        comparison = None
+        if not args.no_compare and not args.no_gap:
+            comparison = compare_equal_accuracy(
+                ctx, bounds, dict(wl, name=args.workload), store, g,
+                lambda d: ctx.search(bounds, d, wl["search_seed"], rescore_fp64=True))
 
     if wl["de"]["ens_enabled"]:
         expect = ens.evals_ens(P_d, de["np_lo"], de["ng_f"], de["np_bf"], de["ng_bf"],
@@ -177,14 +238,16 @@ def main():
     gbs = bytes_per_launch / per_launch_s / 1e9
     tflops = flops_per_launch / per_launch_s / 1e12
     prof = measured_traffic(args.workload)
+    kname = ("k_search_dense" if ex.get("dense") else "k_search") + \
+        f"<{wl['op']}, { {'f32': 0, 'f16': 1, 'bf16': 2}[store]}, {W}, 0>"
     traffic = None
-    if prof is not None and prof["kernel"].startswith(f"void ens::k_search<{wl['op']}, "):
+    if prof is not None and prof["kernel"] == f"void ens::{kname}(ens::SearchArgs)":
         traffic = round(prof["traffic_bytes_per_launch"])
     roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": FP32_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": round(tflops / FP32_PEAK_TFLOPS, 4), "traffic": traffic,
             "flops_per_pair": flops_per_pair(wl["op"], W),
             "algorithmic_bytes_per_launch": round(bytes_per_launch),
-            "kernel": f"k_search<{wl['op']},{ {'f32': 0, 'f16': 1, 'bf16': 2}[store]},{W},0>",
+            "kernel": kname,
             "launches": ex["launches"], "avg_launch_ms": round(ex["device_ms"] / ex["launches"], 4),
             "algorithmic_gather": {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                    "frac": round(gbs / HBM_PEAK_GBS, 4)}}
@@ -210,6 +273,7 @@ def main():
         "gap_ok": None if not gap or "mean" not in gap else bool(gap["mean"] <= 1e-3),
         "roofline": roof,
         "stats": st,
+        "equal_accuracy": comparison,
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(g, wl, de, bounds)

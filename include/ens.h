@@ -171,12 +171,19 @@ typedef struct {
     const float *params;
 } ens_candidates;
 
-/* Search-kernel launch shape; zero fields mean "let the library choose". */
+/* Search-kernel launch shape.  Zero fields are chosen by measurement: the
+ * first search of a given shape times its first launch of each kernel kind
+ * for every (slices, order) pair and keeps the fastest for later searches on
+ * the same context. */
 typedef struct {
     uint32_t struct_size;
-    int32_t waves_per_sample_group;  /* trace slices per population (1, 2, 4, 8) */
+    int32_t waves_per_sample_group;  /* trace slices per population (1, 2, 4, 8); 0: measure */
     int32_t use_graph;               /* 1: replay the trace-step launches as a HIP graph */
     int32_t collect_timing;          /* 1: time every search launch with HIP events */
+    int32_t item_order;              /* 0: measure; 1: XCD-contiguous (bucket, t) order;
+                                        2: costliest items first, dealt round-robin */
+    int32_t occupancy;               /* 0: measure; 1: registers as compiled (5 waves per SIMD);
+                                        2: held to 64 registers (8 waves per SIMD) */
 } ens_tuning;
 
 /* Work and device time of the last ens_search, per kernel kind:
@@ -192,6 +199,10 @@ typedef struct {
     int64_t evals[4];
     int64_t sum_m[4];
     double device_ms[4];
+    int32_t waves_used[2];   /* trace slices chosen for kinds [0] and [1] */
+    int32_t order_used[2];   /* item order chosen (1 or 2) for kinds [0] and [1] */
+    int32_t dense_used[2];   /* 1 if the 64-register variant was chosen */
+    double tune_ms;          /* device time spent measuring launch shapes in this call */
 } ens_stats;
 
 /* ---- context ----------------------------------------------------------- */

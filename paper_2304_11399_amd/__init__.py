@@ -80,13 +80,16 @@ class Candidates(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("waves_per_sample_group", C.c_int32),
-                ("use_graph", C.c_int32), ("collect_timing", C.c_int32)]
+                ("use_graph", C.c_int32), ("collect_timing", C.c_int32), ("item_order", C.c_int32),
+                ("occupancy", C.c_int32)]
 
 
 class Stats(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("launches", C.c_int64 * 4),
                 ("evals", C.c_int64 * 4), ("sum_m", C.c_int64 * 4),
-                ("device_ms", C.c_double * 4)]
+                ("device_ms", C.c_double * 4), ("waves_used", C.c_int32 * 2),
+                ("order_used", C.c_int32 * 2), ("dense_used", C.c_int32 * 2),
+                ("tune_ms", C.c_double)]
 
 
 STAT_KINDS = ("explore", "exploit", "polish", "rescore64")
@@ -184,9 +187,11 @@ class Context:
     def last_error(self):
         return self._lib.ens_last_error(self._h).decode()
 
-    def set_tuning(self, waves_per_sample_group=0, use_graph=0, collect_timing=0):
+    def set_tuning(self, waves_per_sample_group=0, use_graph=0, collect_timing=0, item_order=0,
+                   occupancy=0):
+        """Launch shape of the search kernels; 0 = chosen by measurement."""
         t = _sized(Tuning, waves_per_sample_group=waves_per_sample_group, use_graph=use_graph,
-                   collect_timing=collect_timing)
+                   collect_timing=collect_timing, item_order=item_order, occupancy=occupancy)
         self._check(self._lib.ens_set_tuning(self._h, C.byref(t)))
 
     def stats(self):
@@ -194,9 +199,15 @@ class Context:
         the last search."""
         st = _sized(Stats)
         self._check(self._lib.ens_last_stats(self._h, C.byref(st)))
-        return {k: dict(launches=int(st.launches[i]), evals=int(st.evals[i]),
-                        sum_m=int(st.sum_m[i]), device_ms=float(st.device_ms[i]))
-                for i, k in enumerate(STAT_KINDS)}
+        d = {k: dict(launches=int(st.launches[i]), evals=int(st.evals[i]),
+                     sum_m=int(st.sum_m[i]), device_ms=float(st.device_ms[i]))
+             for i, k in enumerate(STAT_KINDS)}
+        for i, k in enumerate(STAT_KINDS[:2]):
+            d[k]["waves"] = int(st.waves_used[i])
+            d[k]["item_order"] = int(st.order_used[i])
+            d[k]["dense"] = int(st.dense_used[i])
+        d["tune_ms"] = float(st.tune_ms)
+        return d
 
     # -------------------------------------------------------------- data
     def bind(self, traces, cmp_ptr, offset, dt, dx, op, window, ap_lo=0, ap_hi=None,

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -68,9 +69,14 @@ struct ens_ctx {
     // next search issues exactly the same launches)
     struct Launch {
         ens::SearchArgs a;
-        int32_t kind, n_blocks;
+        int32_t kind, n_blocks, dense;
     };
     std::vector<Launch> graph_seq;
+    // measured launch shapes: key -> (slices, item order)
+    struct Shape {
+        int nsl, order, dense;
+    };
+    std::map<std::string, Shape> tune_cache;
     hipGraphExec_t graph_exec = nullptr;
     hipGraph_t graph = nullptr;
     void drop_graph()
@@ -191,6 +197,10 @@ ens_status ens_set_tuning(ens_ctx *ctx, const ens_tuning *t)
         return fail(ctx, ENS_E_RANGE, "waves_per_sample_group must be 0, 1, 2, 4 or 8 (got %d)", w);
     if (t->use_graph && t->collect_timing)
         return fail(ctx, ENS_E_INVALID, "use_graph and collect_timing exclude each other");
+    if (t->item_order < 0 || t->item_order > 2)
+        return fail(ctx, ENS_E_RANGE, "item_order must be 0, 1 or 2 (got %d)", t->item_order);
+    if (t->occupancy < 0 || t->occupancy > 2)
+        return fail(ctx, ENS_E_RANGE, "occupancy must be 0, 1 or 2 (got %d)", t->occupancy);
     ctx->tuning = *t;
     ctx->err.clear();
     return ENS_OK;
@@ -346,33 +356,49 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
     std::vector<int32_t> cmp_out(static_cast<size_t>(n_out));
     for (int32_t o = 0; o < n_out; ++o) cmp_out[o] = grid->cmp_out ? grid->cmp_out[o] : o;
 
-    // work items: consecutive t with equal NP packed floor(64/NP) per wave
-    auto build_items = [&](int32_t n_groups, bool per_stage0, std::vector<int4> &items) {
+    // work items: consecutive t with equal NP packed floor(64/NP) per wave, in
+    // (group, t) order; the second copy puts the costliest items first
+    const double traces_per_cmp = static_cast<double>(ctx->n_tr) / ctx->n_cmp;
+    auto build_items = [&](int32_t n_groups, bool stage0, std::vector<int4> &items) {
         for (int32_t gidx = 0; gidx < n_groups; ++gidx) {
             int32_t t = t_begin;
             while (t < grid->t_end) {
-                const int32_t np = per_stage0 ? lerp_round(de->np_lo, de->np_hi, t, nt) : de->np_bf;
+                const int32_t np = stage0 ? lerp_round(de->np_lo, de->np_hi, t, nt) : de->np_bf;
                 const int32_t per = ens::WAVE / np;
                 int32_t ns = 1;
                 while (ns < per && t + ns < grid->t_end &&
-                       (per_stage0 ? lerp_round(de->np_lo, de->np_hi, t + ns, nt) : de->np_bf) == np)
+                       (stage0 ? lerp_round(de->np_lo, de->np_hi, t + ns, nt) : de->np_bf) == np)
                     ++ns;
                 items.push_back(make_int4(gidx, t, ns, np));
                 t += ns;
             }
         }
     };
+    auto costliest_first = [&](const std::vector<int4> &items) {
+        std::vector<int4> v = items;
+        auto cost = [&](const int4 &it) {
+            const int32_t tm = it.y + it.z - 1;
+            const int32_t ap = lerp_round(ctx->ap_lo, ctx->ap_hi, tm, nt);
+            return static_cast<double>(it.z) * it.w * (2 * ap + 1) * traces_per_cmp;
+        };
+        std::stable_sort(v.begin(), v.end(), [&](const int4 &x, const int4 &y) { return cost(x) > cost(y); });
+        return v;
+    };
     const bool ens = de->ens_enabled != 0;
     const int32_t n_buckets = ens ? (n_out + de->n_bucket - 1) / de->n_bucket : 0;
     std::vector<int4> items0, items_bf;
     build_items(ens ? n_buckets : n_out, true, items0);
     if (ens && de->n_cycle > 0) build_items(n_buckets, false, items_bf);
+    const std::vector<int4> items0_lpt = costliest_first(items0), items_bf_lpt = costliest_first(items_bf);
+    // device layout: [items0 | items0 costliest-first | items_bf | items_bf costliest-first]
+    const size_t off0[3] = {0, 0, items0.size()};
+    const size_t offbf[3] = {0, 2 * items0.size(), 2 * items0.size() + items_bf.size()};
 
     const size_t pbytes = sizeof(float) * static_cast<size_t>(n_s) * P, sbytes = sizeof(float) * n_s;
     HIP_OR_FAIL(ctx, ctx->lo_tab.ensure(lo.size() * sizeof(float)));
     HIP_OR_FAIL(ctx, ctx->hi_tab.ensure(hi.size() * sizeof(float)));
     HIP_OR_FAIL(ctx, ctx->cmp_out.ensure(cmp_out.size() * sizeof(int32_t)));
-    HIP_OR_FAIL(ctx, ctx->items.ensure((items0.size() + items_bf.size()) * sizeof(int4)));
+    HIP_OR_FAIL(ctx, ctx->items.ensure(2 * (items0.size() + items_bf.size()) * sizeof(int4)));
     HIP_OR_FAIL(ctx, ctx->counters.ensure(8 * sizeof(unsigned long long)));
     if (ens) {
         HIP_OR_FAIL(ctx, ctx->X.ensure(pbytes));
@@ -384,12 +410,13 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
     HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->hi_tab.p, hi.data(), hi.size() * sizeof(float), hipMemcpyHostToDevice, st));
     HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->cmp_out.p, cmp_out.data(), cmp_out.size() * sizeof(int32_t),
                                     hipMemcpyHostToDevice, st));
-    HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->items.p, items0.data(), items0.size() * sizeof(int4),
-                                    hipMemcpyHostToDevice, st));
-    if (!items_bf.empty())
-        HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->items.as<int4>() + items0.size(), items_bf.data(),
-                                        items_bf.size() * sizeof(int4), hipMemcpyHostToDevice, st));
-    HIP_OR_FAIL(ctx, hipMemsetAsync(ctx->counters.p, 0, 8 * sizeof(unsigned long long), st));
+    int4 *dev_items = ctx->items.as<int4>();
+    const std::vector<int4> *parts[4] = {&items0, &items0_lpt, &items_bf, &items_bf_lpt};
+    const size_t part_off[4] = {off0[1], off0[2], offbf[1], offbf[2]};
+    for (int q = 0; q < 4; ++q)
+        if (!parts[q]->empty())
+            HIP_OR_FAIL(ctx, hipMemcpyAsync(dev_items + part_off[q], parts[q]->data(), parts[q]->size() * sizeof(int4),
+                                            hipMemcpyHostToDevice, st));
 
     float *final_params = nullptr, *final_S = nullptr;
     ens::SearchArgs a{};
@@ -402,41 +429,44 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
     a.hi_tab = ctx->hi_tab.as<float>();
     a.n_bucket = de->n_bucket;
     a.inject = de->inject;
-    a.nsl = ctx->tuning.waves_per_sample_group > 0 ? ctx->tuning.waves_per_sample_group : 4;
     a.seed = seed;
     a.F = de->F;
     a.cr_thr = static_cast<uint64_t>(std::ceil(static_cast<double>(de->CR) * 4294967296.0));
     a.counters = ctx->counters.as<unsigned long long>();
 
-    // launch sequence of the evolution
+    // launch sequence of the evolution (slices and item order filled in below)
     std::vector<ens_ctx::Launch> seq;
     if (!ens) {
-        a.items = ctx->items.as<int4>();
         a.n_items = static_cast<int32_t>(items0.size());
         a.plain = 1;
         a.stage = 0;
+        a.k_begin = 0;
+        a.k_end = 1;
         a.ng = de->ng_f;
         a.Yp = out->params;
         a.YS = out->S;
-        seq.push_back({a, 0, a.n_items});
+        seq.push_back({a, 0, a.n_items, 0});
     } else {
         float *X = ctx->X.as<float>(), *XS = ctx->XS.as<float>();
         float *Y = ctx->Y.as<float>(), *YS = ctx->YS.as<float>();
         a.plain = 0;
         const int32_t n_stage = 1 + 2 * de->n_cycle;
+        // a stage's sweep is split into launches of at most STEPS trace steps
+        constexpr int32_t STEPS = 32;
+        const int32_t n_steps = std::min(de->n_bucket, n_out);
         for (int32_t s = 0; s < n_stage; ++s) {
             a.stage = s;
             a.forward = (s % 2 == 0) ? 1 : 0;
             a.ng = s == 0 ? de->ng_f : de->ng_bf;
-            a.items = ctx->items.as<int4>() + (s == 0 ? 0 : items0.size());
             a.n_items = static_cast<int32_t>(s == 0 ? items0.size() : items_bf.size());
             a.Xp = X;
             a.XS = XS;
             a.Yp = Y;
             a.YS = YS;
-            for (int32_t k = 0; k < de->n_bucket && k < n_out; ++k) {
-                a.k = k;
-                seq.push_back({a, s == 0 ? 0 : 1, a.n_items});
+            for (int32_t k0 = 0; k0 < n_steps; k0 += STEPS) {
+                a.k_begin = k0;
+                a.k_end = std::min(n_steps, k0 + STEPS);
+                seq.push_back({a, s == 0 ? 0 : 1, a.n_items, 0});
             }
             std::swap(X, Y);
             std::swap(XS, YS);
@@ -446,6 +476,93 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
     }
     ctx->stats = ens_stats{};
     ctx->stats.struct_size = sizeof(ens_stats);
+
+    // launch shape per kernel kind: fixed by the caller, cached, or measured
+    for (int kind = 0; kind < 2; ++kind) {
+        const ens_ctx::Launch *first = nullptr;
+        for (const auto &l : seq)
+            if (l.kind == kind) {
+                first = &l;
+                break;
+            }
+        if (!first) continue;
+        char key[256];
+        snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d", kind, P, ctx->store_dtype, ctx->window,
+                 de->np_lo, de->np_hi, first->a.ng, first->n_blocks, n_out, n_t, ctx->ap_hi);
+        int nsl = ctx->tuning.waves_per_sample_group, order = ctx->tuning.item_order;
+        int dense = ctx->tuning.occupancy == 0 ? -1 : (ctx->tuning.occupancy == 2 ? 1 : 0);
+        if (nsl == 0 || order == 0 || dense < 0) {
+            auto hit = ctx->tune_cache.find(key);
+            if (hit != ctx->tune_cache.end()) {
+                if (nsl == 0) nsl = hit->second.nsl;
+                if (order == 0) order = hit->second.order;
+                if (dense < 0) dense = hit->second.dense;
+            }
+        }
+        if (nsl == 0 || order == 0 || dense < 0) {
+            // time the first launch of this kind for every candidate shape
+            const int nsl_opts[4] = {1, 2, 4, 8};
+            std::vector<ens_ctx::Shape> cands;
+            for (int ns : nsl_opts)
+                for (int od = 1; od <= 2; ++od)
+                    for (int dn = 0; dn <= 1; ++dn)
+                        if ((nsl == 0 || ns == nsl) && (order == 0 || od == order) && (dense < 0 || dn == dense))
+                            cands.push_back({ns, od, dn});
+            ens::SearchArgs ta = first->a;
+            if (kind == 1) {
+                HIP_OR_FAIL(ctx, hipMemsetAsync(ctx->X.p, 0, pbytes, st));
+                HIP_OR_FAIL(ctx, hipMemsetAsync(ctx->XS.p, 0, sbytes, st));
+                HIP_OR_FAIL(ctx, hipMemsetAsync(ctx->Y.p, 0, pbytes, st));
+                HIP_OR_FAIL(ctx, hipMemsetAsync(ctx->YS.p, 0, sbytes, st));
+            }
+            while (ctx->events.size() < 2 * cands.size()) {
+                hipEvent_t e;
+                HIP_OR_FAIL(ctx, hipEventCreate(&e));
+                ctx->events.push_back(e);
+            }
+            for (int warm = 0; warm <= 1; ++warm) {  // load both kernel variants once
+                ta.nsl = cands[0].nsl;
+                ta.xcd_order = 1;
+                ta.items = dev_items + (kind == 0 ? off0[1] : offbf[1]);
+                HIP_OR_FAIL(ctx, ens::launch_search(P, ctx->store_dtype, ctx->window, kind, warm, ta,
+                                                    first->n_blocks, st));
+            }
+            for (size_t c = 0; c < cands.size(); ++c) {
+                ta.nsl = cands[c].nsl;
+                ta.xcd_order = cands[c].order == 1;
+                ta.items = dev_items + (kind == 0 ? off0[cands[c].order] : offbf[cands[c].order]);
+                HIP_OR_FAIL(ctx, hipEventRecord(ctx->events[2 * c], st));
+                HIP_OR_FAIL(ctx, ens::launch_search(P, ctx->store_dtype, ctx->window, kind, cands[c].dense, ta,
+                                                    first->n_blocks, st));
+                HIP_OR_FAIL(ctx, hipEventRecord(ctx->events[2 * c + 1], st));
+            }
+            HIP_OR_FAIL(ctx, hipStreamSynchronize(st));
+            float best = 0.f;
+            for (size_t c = 0; c < cands.size(); ++c) {
+                float ms = 0.f;
+                HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms, ctx->events[2 * c], ctx->events[2 * c + 1]));
+                ctx->stats.tune_ms += ms;
+                if (c == 0 || ms < best) {
+                    best = ms;
+                    nsl = cands[c].nsl;
+                    order = cands[c].order;
+                    dense = cands[c].dense;
+                }
+            }
+            ctx->tune_cache[key] = {nsl, order, dense};
+        }
+        ctx->stats.waves_used[kind] = nsl;
+        ctx->stats.order_used[kind] = order;
+        ctx->stats.dense_used[kind] = dense;
+        for (auto &l : seq)
+            if (l.kind == kind) {
+                l.a.nsl = nsl;
+                l.a.xcd_order = order == 1;
+                l.a.items = dev_items + (kind == 0 ? off0[order] : offbf[order]);
+                l.dense = dense;
+            }
+    }
+    HIP_OR_FAIL(ctx, hipMemsetAsync(ctx->counters.p, 0, 8 * sizeof(unsigned long long), st));
     for (const auto &l : seq) ctx->stats.launches[l.kind] += 1;
     const bool timing = ctx->tuning.collect_timing != 0;
     const bool graph = ctx->tuning.use_graph != 0 && !timing;
@@ -465,7 +582,7 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
             HIP_OR_FAIL(ctx, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
             hipError_t le = hipSuccess;
             for (const auto &l : seq) {
-                le = ens::launch_search(P, ctx->store_dtype, ctx->window, l.kind, l.a, l.n_blocks, st);
+                le = ens::launch_search(P, ctx->store_dtype, ctx->window, l.kind, l.dense, l.a, l.n_blocks, st);
                 if (le != hipSuccess) break;
             }
             hipGraph_t gph = nullptr;
@@ -481,7 +598,7 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
         for (size_t i = 0; i < seq.size(); ++i) {
             const auto &l = seq[i];
             if (timing) HIP_OR_FAIL(ctx, hipEventRecord(ctx->events[2 * i], st));
-            HIP_OR_FAIL(ctx, ens::launch_search(P, ctx->store_dtype, ctx->window, l.kind, l.a, l.n_blocks, st));
+            HIP_OR_FAIL(ctx, ens::launch_search(P, ctx->store_dtype, ctx->window, l.kind, l.dense, l.a, l.n_blocks, st));
             if (timing) HIP_OR_FAIL(ctx, hipEventRecord(ctx->events[2 * i + 1], st));
         }
     }

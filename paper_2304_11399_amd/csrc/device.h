@@ -67,11 +67,22 @@ __device__ __forceinline__ float f16_bits_to_f32(uint32_t b)
 typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
 typedef float f2u __attribute__((ext_vector_type(2), aligned(4)));
 
-// Load N consecutive stored samples starting at p as binary32.
+typedef uint32_t u4u __attribute__((ext_vector_type(4), aligned(4)));
+
+__device__ __forceinline__ float half_to_f32(uint32_t bits16, int DT)
+{
+    return DT == DT_F16 ? f16_bits_to_f32(bits16) : bf16_bits_to_f32(bits16);
+}
+
+// Load N (even for 16-bit storage) consecutive stored samples starting at
+// element `off` of row `row` as binary32.  16-bit rows are read as aligned
+// dwords, N/2 + 1 of them, and realigned by a funnel shift when `off` is odd.
 template <int DT, int N>
-__device__ __forceinline__ void load_window(const typename Store<DT>::T *__restrict__ p, float *u)
+__device__ __forceinline__ void load_window(const typename Store<DT>::T *__restrict__ row, uint32_t off,
+                                            float *u)
 {
     if constexpr (DT == DT_F32) {
+        const float *p = row + off;
         int k = 0;
 #pragma unroll
         for (; k + 4 <= N; k += 4) {
@@ -85,10 +96,24 @@ __device__ __forceinline__ void load_window(const typename Store<DT>::T *__restr
         }
         if constexpr (N % 2 == 1) u[k] = p[k];
     } else {
+        static_assert(N % 2 == 0, "16-bit windows hold an even number of samples");
+        constexpr int ND = N / 2 + 1;
+        const uint32_t *q = reinterpret_cast<const uint32_t *>(row + (off & ~1u));
+        const uint32_t shift = (off & 1u) << 4;
+        uint32_t d[ND];
+        int k = 0;
 #pragma unroll
-        for (int k = 0; k < N; ++k) {
-            const uint32_t b = p[k];
-            u[k] = DT == DT_F16 ? f16_bits_to_f32(b) : bf16_bits_to_f32(b);
+        for (; k + 4 <= ND; k += 4) {
+            const u4u v = *reinterpret_cast<const u4u *>(q + k);
+            d[k] = v.x; d[k + 1] = v.y; d[k + 2] = v.z; d[k + 3] = v.w;
+        }
+#pragma unroll
+        for (; k < ND; ++k) d[k] = q[k];
+#pragma unroll
+        for (int m = 0; m < N / 2; ++m) {
+            const uint32_t w = __builtin_amdgcn_alignbit(d[m + 1], d[m], shift);
+            u[2 * m] = half_to_f32(w & 0xffffu, DT);
+            u[2 * m + 1] = half_to_f32(w >> 16, DT);
         }
     }
 }
@@ -239,10 +264,12 @@ __device__ __forceinline__ void accum_trace(Acc<W, R> &acc, const Cand<R> &c, co
     }
     acc.M += tt.ok ? 1 : 0;
     float u[W + 1];
-    load_window<DT, W + 1>(row + tt.off, u);
+    load_window<DT, W + 1>(row, tt.off, u);
 #pragma unroll
     for (int k = 0; k < W; ++k) {
-        const R a = fmadd(wb, static_cast<R>(u[k + 1]), wa * static_cast<R>(u[k]));
+        // written as two fused steps so that binary16 samples feed the
+        // mixed-precision FMA without a separate conversion
+        const R a = fmadd(wb, static_cast<R>(u[k + 1]), fmadd(wa, static_cast<R>(u[k]), R(0)));
         acc.s[k] += a;
         acc.E = fmadd(a, a, acc.E);
     }

@@ -244,7 +244,7 @@ __device__ __forceinline__ float semblance_grad_lane(const StoreView &sv, const 
             const bool use = nonzero && tt.ok && tt.tau > 0.0f;
             const float sc = sv.scale ? sv.scale[i] : 1.0f;
             float u[W + 1];
-            load_window<DT, W + 1>(store + static_cast<size_t>(i) * sv.ld + tt.off, u);
+            load_window<DT, W + 1>(store + static_cast<size_t>(i) * sv.ld, tt.off, u);
             const float wa = (1.0f - tt.f) * sc, wb = tt.f * sc;
             float dSdtau = 0.0f;
 #pragma unroll
@@ -375,29 +375,34 @@ __device__ __forceinline__ float eval_slices(const StoreView &sv, const Cand<flo
     return finish_semblance(acc);
 }
 
-// Evolution of a group of samples of one output CMP: lane = (sample, slot),
-// floor(64/NP) samples per wave, the trace loop split over nsl waves.  The
-// whole evolution (initial population and NG generations) runs in one
-// launch; with ENS, one launch is one trace step of a sweep in every bucket.
+// Evolution of a group of samples: lane = (sample, slot), floor(64/NP)
+// samples of one output CMP per wave, the trace loop split over nsl waves.
+// Plain search: each workgroup runs the whole evolution (initial population
+// and NG generations) of its samples.  ENS: each workgroup sweeps its time
+// samples through the traces of its bucket, one trace after another: within
+// a stage, sample (t, trace) depends only on (t, previous trace) of the same
+// stage and on the complete previous stage, so the sweeps of different t
+// never wait for each other and one launch covers many steps.
 // KIND 0: exploration (plain evolution or ENS stage 0); KIND 1: ENS
 // exploitation stages.  KIND selects the counters and names the kernel.
+// k_search_dense is the same code held to 64 VGPRs (8 waves per SIMD), for
+// launches whose wave count fits the chip in one round at that occupancy.
 template <int OP, int DT, int W, int KIND>
-__global__ __launch_bounds__(512) void k_search(SearchArgs a)
+__device__ __forceinline__ void search_body(const SearchArgs &a)
 {
     extern __shared__ float lds[];
     const int32_t nsl = a.nsl;
     const int32_t wave = __builtin_amdgcn_readfirstlane(static_cast<int32_t>(threadIdx.x) >> 6);
     const int32_t lane = threadIdx.x & (WAVE - 1);
-    const int4 it = a.items[xcd_remap(blockIdx.x, gridDim.x)];
-    int32_t o, prev = -1;
-    if (a.plain) {
-        o = it.x;
-    } else {
-        const int32_t b0 = it.x * a.n_bucket;
-        const int32_t nb = min(a.n_bucket, a.n_out - b0);
-        if (a.k >= nb) return;  // this bucket has no trace at this step
-        o = b0 + (a.forward ? a.k : nb - 1 - a.k);
-        if (a.k > 0) prev = a.forward ? o - 1 : o + 1;
+    const int4 it = a.items[a.xcd_order ? xcd_remap(blockIdx.x, gridDim.x) : static_cast<int32_t>(blockIdx.x)];
+    // the traces this workgroup sweeps: one for the plain search, else the
+    // steps [k_begin, k_end) of its bucket's sweep (fewer for a short bucket)
+    int32_t b0 = 0, nb = 1, k_end = 1, k_begin = 0;
+    if (!a.plain) {
+        b0 = it.x * a.n_bucket;
+        nb = min(a.n_bucket, a.n_out - b0);
+        k_begin = a.k_begin;
+        k_end = min(a.k_end, nb);
     }
     const int32_t t_start = it.y, ns = it.z, np = it.w;
     const int32_t grp = lane / np;
@@ -406,7 +411,6 @@ __global__ __launch_bounds__(512) void k_search(SearchArgs a)
     const int32_t base = grp * np;
     const int32_t n0 = t_start + (live ? grp : ns - 1);
     const int32_t tt = n0 - a.t_begin;
-    const int32_t j = __builtin_amdgcn_readfirstlane(a.cmp_out[o]);
     const int32_t ap = a.sv.ap_tab[n0];
     float lo[3] = {0.f, 0.f, 0.f}, hi[3] = {0.f, 0.f, 0.f};
 #pragma unroll
@@ -416,75 +420,91 @@ __global__ __launch_bounds__(512) void k_search(SearchArgs a)
     }
     // apertures grow or shrink linearly in t: the item's extreme samples bound them
     const int32_t amax = max(a.sv.ap_tab[t_start], a.sv.ap_tab[t_start + ns - 1]);
-    const int32_t c_lo = max(0, j - amax), c_hi = min(a.sv.n_cmp - 1, j + amax);
-    const uint64_t sid = static_cast<uint64_t>(n0) + static_cast<uint64_t>(a.sv.nt) * static_cast<uint64_t>(j);
     const uint64_t stage = static_cast<uint64_t>(a.stage);
-
-    // initial population (section "Initializing") and ENS seeds
-    float x[3] = {0.f, 0.f, 0.f};
-    uint64_t w[4];
-    philox4x64_10(sid, stage, 0, static_cast<uint64_t>(slot), a.seed, 0, w);
-#pragma unroll
-    for (int d = 0; d < OP; ++d) x[d] = init_coord(w[d], lo[d], hi[d]);
-    float S = 0.0f;
-    bool scored = false;
-    if (!a.plain) {
-        const int64_t here = static_cast<int64_t>(o) * a.n_t + tt;
-        const int64_t from_prev = static_cast<int64_t>(prev) * a.n_t + tt;
-        if (a.stage == 0) {
-            if (a.inject && slot == 0 && prev >= 0) load_clamped<OP>(a.Yp + from_prev * OP, lo, hi, x);
-        } else {
-            if (a.inject && slot == 0 && tt > 0) load_clamped<OP>(a.Xp + (here - 1) * OP, lo, hi, x);
-            if (a.inject && slot == 1 && tt < a.n_t - 1) load_clamped<OP>(a.Xp + (here + 1) * OP, lo, hi, x);
-            if (a.inject && slot == 2 && prev >= 0) load_clamped<OP>(a.Yp + from_prev * OP, lo, hi, x);
-            if (slot == 3) {
-#pragma unroll
-                for (int d = 0; d < OP; ++d) x[d] = a.Xp[here * OP + d];
-                S = a.XS[here];
-                scored = true;
-            }
-        }
-    }
     int buf = 0;
     int32_t M = 0;
     uint32_t n_ev = 0;
     uint64_t sum_m = 0;
-    {
-        const Cand<float> cand = make_cand<OP, float>(x, n0, j, ap, a.sv.nt, a.sv.dt, a.sv.dx);
-        const float Sev = eval_slices<DT, W>(a.sv, cand, c_lo, c_hi, wave, nsl, lane, lds, buf, M);
-        if (!scored) {
-            S = Sev;
+    float pbest[3] = {0.f, 0.f, 0.f};  // this sample's best on the previous trace of the sweep
+
+    for (int32_t k = k_begin; k < k_end; ++k) {
+        const int32_t o = a.plain ? it.x : b0 + (a.forward ? k : nb - 1 - k);
+        const int32_t prev = k > 0 ? (a.forward ? o - 1 : o + 1) : -1;
+        const int32_t j = __builtin_amdgcn_readfirstlane(a.cmp_out[o]);
+        const int32_t c_lo = max(0, j - amax), c_hi = min(a.sv.n_cmp - 1, j + amax);
+        const uint64_t sid =
+            static_cast<uint64_t>(n0) + static_cast<uint64_t>(a.sv.nt) * static_cast<uint64_t>(j);
+        const int64_t here = static_cast<int64_t>(o) * a.n_t + tt;
+
+        // initial population (section "Initializing") and ENS seeds
+        float x[3] = {0.f, 0.f, 0.f};
+        uint64_t w[4];
+        philox4x64_10(sid, stage, 0, static_cast<uint64_t>(slot), a.seed, 0, w);
+#pragma unroll
+        for (int d = 0; d < OP; ++d) x[d] = init_coord(w[d], lo[d], hi[d]);
+        float S = 0.0f;
+        bool scored = false;
+        if (!a.plain) {
+            // the previous trace of this sweep: kept in registers within the
+            // launch, read back from the stage state at a launch's first step
+            const int prev_slot = a.stage == 0 ? 0 : 2;
+            if (a.inject && slot == prev_slot && prev >= 0) {
+                if (k > k_begin) {
+#pragma unroll
+                    for (int d = 0; d < OP; ++d) x[d] = fminf(fmaxf(pbest[d], lo[d]), hi[d]);
+                } else {
+                    load_clamped<OP>(a.Yp + (static_cast<int64_t>(prev) * a.n_t + tt) * OP, lo, hi, x);
+                }
+            }
+            if (a.stage > 0) {
+                if (a.inject && slot == 0 && tt > 0) load_clamped<OP>(a.Xp + (here - 1) * OP, lo, hi, x);
+                if (a.inject && slot == 1 && tt < a.n_t - 1) load_clamped<OP>(a.Xp + (here + 1) * OP, lo, hi, x);
+                if (slot == 3) {
+#pragma unroll
+                    for (int d = 0; d < OP; ++d) x[d] = a.Xp[here * OP + d];
+                    S = a.XS[here];
+                    scored = true;
+                }
+            }
+        }
+        {
+            const Cand<float> cand = make_cand<OP, float>(x, n0, j, ap, a.sv.nt, a.sv.dt, a.sv.dx);
+            const float Sev = eval_slices<DT, W>(a.sv, cand, c_lo, c_hi, wave, nsl, lane, lds, buf, M);
+            if (!scored) {
+                S = Sev;
+                if (live) {
+                    n_ev += 1;
+                    sum_m += static_cast<uint64_t>(M);
+                }
+            }
+        }
+        // generations (sections "Mutation and crossover", "Selection")
+        for (int32_t g = 1; g <= a.ng; ++g) {
+            philox4x64_10(sid, stage, static_cast<uint64_t>(g), static_cast<uint64_t>(slot), a.seed, 0, w);
+            float u[3] = {0.f, 0.f, 0.f};
+            make_trial<OP>(x, S, base, np, slot, w, a.F, a.cr_thr, lo, hi, u);
+            const Cand<float> cand = make_cand<OP, float>(u, n0, j, ap, a.sv.nt, a.sv.dt, a.sv.dx);
+            const float St = eval_slices<DT, W>(a.sv, cand, c_lo, c_hi, wave, nsl, lane, lds, buf, M);
             if (live) {
                 n_ev += 1;
                 sum_m += static_cast<uint64_t>(M);
             }
-        }
-    }
-    // generations (sections "Mutation and crossover", "Selection")
-    for (int32_t g = 1; g <= a.ng; ++g) {
-        philox4x64_10(sid, stage, static_cast<uint64_t>(g), static_cast<uint64_t>(slot), a.seed, 0, w);
-        float u[3] = {0.f, 0.f, 0.f};
-        make_trial<OP>(x, S, base, np, slot, w, a.F, a.cr_thr, lo, hi, u);
-        const Cand<float> cand = make_cand<OP, float>(u, n0, j, ap, a.sv.nt, a.sv.dt, a.sv.dx);
-        const float St = eval_slices<DT, W>(a.sv, cand, c_lo, c_hi, wave, nsl, lane, lds, buf, M);
-        if (live) {
-            n_ev += 1;
-            sum_m += static_cast<uint64_t>(M);
-        }
-        if (St >= S) {
+            if (St >= S) {
 #pragma unroll
-            for (int d = 0; d < OP; ++d) x[d] = u[d];
-            S = St;
+                for (int d = 0; d < OP; ++d) x[d] = u[d];
+                S = St;
+            }
         }
-    }
-    const int32_t b = group_argmax(S, base, np);
-    if (wave == 0) {
-        if (live && slot == b) {
-            const int64_t here = static_cast<int64_t>(o) * a.n_t + tt;
+        const int32_t b = group_argmax(S, base, np);
+#pragma unroll
+        for (int d = 0; d < OP; ++d) pbest[d] = __shfl(x[d], base + b, WAVE);
+        if (wave == 0 && live && slot == b) {
 #pragma unroll
             for (int d = 0; d < OP; ++d) a.Yp[here * OP + d] = x[d];
             a.YS[here] = S;
         }
+    }
+    if (wave == 0) {
         const uint64_t tot_ev = wave_sum(static_cast<uint64_t>(n_ev));
         const uint64_t tot_m = wave_sum(sum_m);
         if (lane == 0) {
@@ -492,6 +512,18 @@ __global__ __launch_bounds__(512) void k_search(SearchArgs a)
             atomicAdd(a.counters + 2 * KIND + 1, static_cast<unsigned long long>(tot_m));
         }
     }
+}
+
+template <int OP, int DT, int W, int KIND>
+__global__ __launch_bounds__(512) void k_search(SearchArgs a)
+{
+    search_body<OP, DT, W, KIND>(a);
+}
+
+template <int OP, int DT, int W, int KIND>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_search_dense(SearchArgs a)
+{
+    search_body<OP, DT, W, KIND>(a);
 }
 
 // Gradient polish of each grid sample's winner: Adam (beta1 0.9, beta2 0.999,
@@ -708,19 +740,24 @@ hipError_t launch_backward(int op, int dtype, int window, const StoreView &sv, c
     return hipGetLastError();
 }
 
-hipError_t launch_search(int op, int dtype, int window, int kind, const SearchArgs &a,
+hipError_t launch_search(int op, int dtype, int window, int kind, int dense, const SearchArgs &a,
                          int32_t n_blocks, hipStream_t s)
 {
     if (n_blocks == 0) return hipSuccess;
     const size_t lds = a.nsl > 1 ? sizeof(float) * 2 * a.nsl * (window + 2) * WAVE : 0;
-    if (kind == 0) {
+    const dim3 grid(static_cast<unsigned>(n_blocks)), block(WAVE * a.nsl);
+    if (kind == 0 && !dense) {
         ENS_DISPATCH_OP(op, ENS_DISPATCH_DT(dtype, ENS_DISPATCH_W(window,
-            hipLaunchKernelGGL((k_search<OP, DT, W, 0>), dim3(static_cast<unsigned>(n_blocks)),
-                               dim3(WAVE * a.nsl), lds, s, a))));
+            hipLaunchKernelGGL((k_search<OP, DT, W, 0>), grid, block, lds, s, a))));
+    } else if (kind == 0) {
+        ENS_DISPATCH_OP(op, ENS_DISPATCH_DT(dtype, ENS_DISPATCH_W(window,
+            hipLaunchKernelGGL((k_search_dense<OP, DT, W, 0>), grid, block, lds, s, a))));
+    } else if (!dense) {
+        ENS_DISPATCH_OP(op, ENS_DISPATCH_DT(dtype, ENS_DISPATCH_W(window,
+            hipLaunchKernelGGL((k_search<OP, DT, W, 1>), grid, block, lds, s, a))));
     } else {
         ENS_DISPATCH_OP(op, ENS_DISPATCH_DT(dtype, ENS_DISPATCH_W(window,
-            hipLaunchKernelGGL((k_search<OP, DT, W, 1>), dim3(static_cast<unsigned>(n_blocks)),
-                               dim3(WAVE * a.nsl), lds, s, a))));
+            hipLaunchKernelGGL((k_search_dense<OP, DT, W, 1>), grid, block, lds, s, a))));
     }
     return hipGetLastError();
 }

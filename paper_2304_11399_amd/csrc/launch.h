@@ -29,7 +29,8 @@ struct CandView {
 };
 
 // One launch of the evolution: either every sample of the grid evolving on
-// its own (plain), or one trace step of an ENS sweep over all buckets.
+// its own (plain), or the trace steps [k_begin, k_end) of one ENS stage in
+// every bucket.
 struct SearchArgs {
     StoreView sv;
     const int32_t *cmp_out;   // [n_out] output CMPs
@@ -37,7 +38,8 @@ struct SearchArgs {
     const float *lo_tab, *hi_tab;  // [nt][3] per-time boxes
     const int4 *items;        // work items {output index or bucket, first t, samples, NP}
     int32_t n_items;
-    int32_t plain, stage, k, forward, n_bucket, ng, inject, nsl;
+    int32_t plain, stage, k_begin, k_end, forward, n_bucket, ng, inject, nsl;
+    int32_t xcd_order;        // 1: deal consecutive items to one XCD; 0: items in block order
     uint64_t seed;
     float F;
     uint64_t cr_thr;          // crossover draw threshold ceil(CR 2^32)
@@ -74,7 +76,7 @@ hipError_t launch_eval64_grid(int op, int window, const StoreView &sv_f32, const
                               double *S, hipStream_t s);
 hipError_t launch_backward(int op, int dtype, int window, const StoreView &sv, const CandView &cv,
                            const float *dS, float *g, hipStream_t s);
-hipError_t launch_search(int op, int dtype, int window, int kind, const SearchArgs &a,
+hipError_t launch_search(int op, int dtype, int window, int kind, int dense, const SearchArgs &a,
                          int32_t n_blocks, hipStream_t s);
 hipError_t launch_polish(int op, int dtype, int window, const PolishArgs &a, hipStream_t s);
 hipError_t launch_philox(int64_t n, const uint64_t *ctr, const uint64_t *key, uint64_t *out,

@@ -27,7 +27,8 @@ OUT = os.path.dirname(os.path.abspath(__file__))
 
 # grid points per axis (A, B t0, C t0): neighbouring points change the far
 # trace's traveltime by about a quarter period of the wavelet
-GRIDS = {"cmp_small": (2049,), "crs_ens": (25, 5, 33), "crs_diff": (29, 5, 41)}
+GRIDS = {"cmp_small": (2049,), "crs_ens": (25, 5, 33), "crs_uneven": (25, 5, 33),
+         "crs_precision": (25, 5, 33), "crs_diff": (29, 5, 41)}
 
 
 def planar_samples(g, wl, n, rng):

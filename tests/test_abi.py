@@ -40,6 +40,8 @@ def test_struct_sizes_match_header_layout():
     assert C.sizeof(ens.Traces) == 48
     assert C.sizeof(ens.DeCfg) == 64
     assert C.sizeof(ens.Result) == 56
+    assert C.sizeof(ens.Stats) == 168
+    assert C.sizeof(ens.Tuning) == 24
 
 
 def test_null_and_state_errors():

@@ -124,6 +124,8 @@ def test_ens_exchange_off_equals_plain_de(ens):
     ctx, g, wl, L = _setup(ens, "crs_ens", n_cmp=12, nt=200)
     base = dict(wl["de"], np_lo=16, np_hi=16, ng_f=6, n_bucket=4, n_cycle=0)
     bounds = base_bounds(wl)
+    # the same launch shape for both, so that the partial sums meet in the same order
+    ctx.set_tuning(waves_per_sample_group=4, item_order=1)
     a = ctx.search(bounds, dict(base, inject=0), seed=5)
     b = ctx.search(bounds, dict(base, ens_enabled=0), seed=5)
     assert torch.equal(a["params"], b["params"]) and torch.equal(a["S"], b["S"])
