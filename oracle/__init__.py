@@ -34,7 +34,8 @@ class _DeCfg(C.Structure):
     _fields_ = [("np_lo", C.c_int32), ("np_hi", C.c_int32), ("ng_f", C.c_int32),
                 ("np_bf", C.c_int32), ("ng_bf", C.c_int32), ("n_cycle", C.c_int32),
                 ("n_bucket", C.c_int32), ("ens_enabled", C.c_int32), ("inject", C.c_int32),
-                ("F", C.c_float), ("CR", C.c_float), ("objective", C.c_int32)]
+                ("F", C.c_float), ("CR", C.c_float), ("objective", C.c_int32),
+                ("n_skip", C.c_int32)]
 
 
 def build(verbose=False):
@@ -201,7 +202,7 @@ def de_cfg(de, objective=0, inject=1):
     return _DeCfg(int(de["np_lo"]), int(de["np_hi"]), int(de["ng_f"]), int(de["np_bf"]),
                   int(de["ng_bf"]), int(de["n_cycle"]), int(de["n_bucket"]),
                   int(de["ens_enabled"]), int(inject), float(de["F"]), float(de["CR"]),
-                  int(objective))
+                  int(objective), int(de.get("n_skip", 0)))
 
 
 def pop_size(de, nt, n0):

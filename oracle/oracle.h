@@ -52,6 +52,7 @@ typedef struct {
     int32_t inject;         /* ENS sweep only: 0 disables every exchange of individuals */
     float F, CR;
     int32_t objective;      /* 0 semblance; 1 sphere mock; 2 needle mock */
+    int32_t n_skip;         /* N_skip: time samples interpolated between estimated ones (0..2) */
 } or_de_cfg;
 
 /* OpenMP threads the oracle's parallel loops use. */

@@ -26,7 +26,7 @@
  * dimensions 0, 1, 2, compared against ceil(CR 2^32).
  *
  * ENS (sections "Information propagation" and "Evolution by neighborhood
- * similarity"), N_skip = 0: stage 0 sweeps each interactive domain (bucket of
+ * similarity"), first with N_skip = 0: stage 0 sweeps each interactive domain (bucket of
  * consecutive output CMPs) left to right with NP_f, NG_f; the best of
  * (t, previous trace) replaces slot 0 of (t, trace).  Each of the N_cycle
  * cycles then sweeps right to left and left to right with NP_bf, NG_bf; slots
@@ -36,6 +36,19 @@
  * its slot random.  All t of one trace step read the state as it was before
  * the step (the t are processed concurrently).  Evaluations per sample:
  * NP_f (1 + NG_f) + N_cycle 2 (NP_bf (1 + NG_bf) - 1) (eq. ens_semblance).
+ *
+ * Time-sample skipping (section "The performance-quality trade-off by an
+ * interpolation process" and the stage definitions of section "Evolution by
+ * neighborhood similarity"), N_skip in {1, 2}: each stage estimates only the
+ * samples t = t_begin + init + m (N_skip + 1), with init 0 for the first
+ * forward sweep, min(1, N_skip) for backward sweeps and N_skip for the later
+ * forward sweeps.  After a trace's estimation the other samples of that
+ * trace take the parameters interpolated linearly in t between the nearest
+ * estimated samples of this stage on either side (the nearest one alone at
+ * the ends of the grid), clamped into their own box, and are scored once.
+ * In the first stage that is their result; in later stages the interpolated
+ * individual replaces the stored one only when it scores higher.  Each
+ * skipped sample costs one evaluation per stage (eq. ens_semblance).
  */
 #include <math.h>
 #include <stdlib.h>
@@ -268,8 +281,10 @@ static int64_t ens_sweep(const objective_ctx *o, const or_bounds *B, uint64_t se
     const int n_stage = 1 + 2 * cfg->n_cycle;
     int64_t total = 0;
 
+    const int32_t stride = cfg->n_skip + 1;
     for (int stage = 0; stage < n_stage; ++stage) {
         const int forward = (stage % 2) == 0;
+        const int32_t init = stage == 0 ? 0 : (forward ? cfg->n_skip : (cfg->n_skip < 1 ? cfg->n_skip : 1));
         for (int32_t b0 = 0; b0 < n_out; b0 += cfg->n_bucket) {
             const int32_t nb = (n_out - b0) < cfg->n_bucket ? (n_out - b0) : cfg->n_bucket;
             for (int32_t k = 0; k < nb; ++k) {
@@ -279,7 +294,7 @@ static int64_t ens_sweep(const objective_ctx *o, const or_bounds *B, uint64_t se
                 const int32_t j = cmp_out[oi];
                 int64_t step_total = 0;
 #pragma omp parallel for schedule(dynamic, 4) reduction(+ : step_total)
-                for (int32_t tt = 0; tt < n_t; ++tt) {
+                for (int32_t tt = init; tt < n_t; tt += stride) {
                     const int32_t n0 = t_begin + tt;
                     const uint64_t sample = (uint64_t)n0 + (uint64_t)L->nt * (uint64_t)j;
                     const int np = stage == 0 ? or_pop_size(cfg, L->nt, n0) : cfg->np_bf;
@@ -332,6 +347,49 @@ static int64_t ens_sweep(const objective_ctx *o, const or_bounds *B, uint64_t se
                     memcpy(Y + here * P, pop + bi * P, sizeof(float) * (size_t)P);
                     YS[here] = S[bi];
                     step_total += ev;
+                }
+                if (stride > 1) {
+                    /* interpolate the skipped samples of this trace */
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : step_total)
+                    for (int32_t tt = 0; tt < n_t; ++tt) {
+                        if (tt >= init && (tt - init) % stride == 0)
+                            continue;
+                        const int32_t n0 = t_begin + tt;
+                        const int64_t here = (int64_t)oi * n_t + tt;
+                        const int32_t ta = tt > init ? tt - (tt - init) % stride : -1;
+                        const int32_t tb_ = tt < init ? init : tt - (tt - init) % stride + stride;
+                        const int32_t tb = tb_ < n_t ? tb_ : -1;
+                        if (ta < 0 && tb < 0) {
+                            /* nothing estimated in this stage: keep the stored individual */
+                            memcpy(Y + here * P, X + here * P, sizeof(float) * (size_t)P);
+                            YS[here] = XS[here];
+                            continue;
+                        }
+                        float lo[3], hi[3], p[3];
+                        or_sample_bounds(L, B, n0, lo, hi);
+                        const float *pa = Y + ((int64_t)oi * n_t + (ta >= 0 ? ta : tb)) * P;
+                        const float *pb = Y + ((int64_t)oi * n_t + (tb >= 0 ? tb : ta)) * P;
+                        if (ta >= 0 && tb >= 0) {
+                            const float wgt = (float)(tt - ta) / (float)(tb - ta);
+                            for (int d = 0; d < P; ++d) {
+                                const float diff = pb[d] - pa[d];
+                                const float step = wgt * diff;
+                                p[d] = pa[d] + step;
+                            }
+                        } else {
+                            memcpy(p, pa, sizeof(float) * (size_t)P);
+                        }
+                        clamp_into(p, P, lo, hi);
+                        const double Sp = objective(o, j, n0, p, lo, hi);
+                        step_total += 1;
+                        if (stage == 0 || Sp > XS[here]) {
+                            memcpy(Y + here * P, p, sizeof(float) * (size_t)P);
+                            YS[here] = Sp;
+                        } else {
+                            memcpy(Y + here * P, X + here * P, sizeof(float) * (size_t)P);
+                            YS[here] = XS[here];
+                        }
+                    }
                 }
                 total += step_total;
             }

@@ -1,5 +1,5 @@
 """Pins of the oracle's ENS sweep (sections "Information propagation" and
-"Evolution by neighborhood similarity", N_skip = 0)."""
+"Evolution by neighborhood similarity"), with and without time-sample skipping."""
 import numpy as np
 import pytest
 
@@ -108,3 +108,55 @@ def test_bucket_edges_do_not_exchange():
     _, Si, _ = L.search(bounds, de, 4, objective=1, inject=0)
     np.testing.assert_array_equal(Sb[3], Si[3])
     np.testing.assert_array_equal(Sb[0], Si[0])
+
+
+# ---------------------------------------------------------------- time skipping
+@pytest.mark.parametrize("n_skip", [1, 2])
+def test_skip_counts_match_paper_formula(small_crs, n_skip):
+    # eq. ens_semblance: ceil(P_d/(N_skip+1)) (S_f + N_cycle S_bf + (2 N_cycle + 1) N_skip),
+    # exact when the grid length is a multiple of N_skip + 1
+    L, bounds = small_crs
+    for n_cycle in (0, 1, 2):
+        de = dict(ENS, n_cycle=n_cycle, n_skip=n_skip)
+        n_t = 60 if n_skip == 2 else 40
+        _, _, ev = L.search(bounds, de, 3, t_begin=50, t_end=50 + n_t)
+        assert ev == evals_ens(L.n_cmp * n_t, 8, 6, 5, 1, n_cycle, n_skip)
+
+
+def test_skip_zero_is_the_plain_sweep(small_crs):
+    L, bounds = small_crs
+    a = L.search(bounds, dict(ENS, n_skip=0), 5, t_begin=100, t_end=140)
+    b = L.search(bounds, ENS, 5, t_begin=100, t_end=140)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+
+
+def test_skipped_samples_lie_between_their_neighbours():
+    # stage 0 only, t-independent box: a skipped sample is the point at
+    # (t - ta)/(tb - ta) along the segment joining the estimated neighbours
+    L = _flat_mock()
+    bounds = (np.array([-1.0, -1.0, -1.0], np.float32), np.array([1.0, 1.0, 1.0], np.float32), 0)
+    de = dict(ENS, np_lo=6, np_hi=6, ng_f=1, n_cycle=0, n_bucket=6, n_skip=2)
+    p, S, _ = L.search(bounds, de, 4, objective=1)
+    n_t = p.shape[1]
+    for o in range(p.shape[0]):
+        for t in range(n_t):
+            if t % 3 == 0:
+                continue
+            ta = t - t % 3
+            tb = ta + 3
+            if tb >= n_t:
+                np.testing.assert_array_equal(p[o, t], p[o, ta])
+                continue
+            w = (t - ta) / 3.0
+            ref = p[o, ta] + w * (p[o, tb] - p[o, ta])
+            np.testing.assert_allclose(p[o, t], ref, rtol=0, atol=1e-6)
+
+
+def test_skip_cycles_never_lower_a_sample(small_crs):
+    L, bounds = small_crs
+    base = dict(ENS, n_skip=2)
+    _, S0, _ = L.search(bounds, dict(base, n_cycle=0), 5, t_begin=120, t_end=180)
+    _, S1, _ = L.search(bounds, dict(base, n_cycle=1), 5, t_begin=120, t_end=180)
+    assert np.all(S1 >= S0)
+    assert np.mean(S1 > S0) > 0.3
