@@ -107,7 +107,8 @@ def cpu_baseline(g, wl, de, bounds):
 
 
 def compare_equal_accuracy(ctx, bounds, wl, store, g, run_main):
-    """ENS against the per-sample search the paper compares with, each over a
+    """ENS (without and with the paper's N_skip = 2 time skipping) against the
+    per-sample search the paper compares with, each over a
     few budgets: the fastest budget whose mean gap to the reference maxima is
     <= 1e-3 is each method's throughput at that accuracy."""
     import torch
@@ -117,6 +118,9 @@ def compare_equal_accuracy(ctx, bounds, wl, store, g, run_main):
                 ("ens", dict(de0, np_lo=16, np_hi=16, ng_f=20)),
                 ("ens", dict(de0, np_lo=16, np_hi=16, ng_f=10)),
                 ("ens", dict(de0, np_lo=8, np_hi=8, ng_f=8)),
+                ("ens_skip2", dict(de0, n_skip=2)),
+                ("ens_skip2", dict(de0, np_lo=16, np_hi=16, ng_f=20, n_skip=2)),
+                ("ens_skip2", dict(de0, np_lo=16, np_hi=16, ng_f=10, n_skip=2)),
                 ("plain", dict(de0, ens_enabled=0, np_lo=16, np_hi=16, ng_f=20)),
                 ("plain", dict(de0, ens_enabled=0, ng_f=40)),
                 ("plain", dict(de0, ens_enabled=0)),
@@ -132,6 +136,7 @@ def compare_equal_accuracy(ctx, bounds, wl, store, g, run_main):
         sec = time.perf_counter() - t0
         gap = gap_stats(wl["name"], out["S64"].cpu().numpy(), g.nt, g)
         rows.append({"method": kind, "np": de["np_lo"], "ng": de["ng_f"],
+                     "n_skip": de.get("n_skip", 0),
                      "ms": round(1e3 * sec, 2), "zo_samples_per_s": round(g.n_cmp * g.nt / sec, 1),
                      "evals": out["n_evals"], "gap_mean": gap["mean"] if gap else None,
                      "frac_le_1e-3": gap["frac_le_1e-3"] if gap else None})
@@ -141,11 +146,13 @@ def compare_equal_accuracy(ctx, bounds, wl, store, g, run_main):
             b = best.get(r["method"])
             if b is None or r["zo_samples_per_s"] > b["zo_samples_per_s"]:
                 best[r["method"]] = r
-    speedup = None
-    if "ens" in best and "plain" in best:
-        speedup = round(best["ens"]["zo_samples_per_s"] / best["plain"]["zo_samples_per_s"], 3)
+    def ratio(a, b):
+        if a in best and b in best:
+            return round(best[a]["zo_samples_per_s"] / best[b]["zo_samples_per_s"], 3)
+        return None
     return {"store": store, "runs": rows, "best_at_gap_le_1e-3": best,
-            "ens_over_plain_zo_samples_per_s": speedup}
+            "ens_over_plain_zo_samples_per_s": ratio("ens", "plain"),
+            "ens_skip2_over_plain_zo_samples_per_s": ratio("ens_skip2", "plain")}
 
 
 def gap_stats(name, S64, nt, g):
@@ -223,7 +230,7 @@ def main():
 
     if wl["de"]["ens_enabled"]:
         expect = ens.evals_ens(P_d, de["np_lo"], de["ng_f"], de["np_bf"], de["ng_bf"],
-                               de["n_cycle"])
+                               de["n_cycle"], de.get("n_skip", 0))
     else:
         expect = ens.evals_jade(P_d, de["np_lo"], de["ng_f"])
     assert de["np_lo"] != de["np_hi"] or evals == expect, (evals, expect)

@@ -52,7 +52,7 @@ typedef enum {
     ENS_OK = 0,
     ENS_E_INVALID = -1,     /* null pointer, bad dtype/op, inconsistent sizes, struct_size */
     ENS_E_RANGE = -2,       /* even or too large window, NP < 4 or > 64, NP_bf < 5, lo >= hi,
-                               n_skip != 0, index out of range */
+                               n_skip outside 0..2 or without ENS, index out of range */
     ENS_E_HIP = -3,         /* a HIP runtime call failed (message has the HIP error string) */
     ENS_E_OOM = -4,         /* device allocation failed */
     ENS_E_UNSUPPORTED = -5, /* valid request this build does not implement */
@@ -127,7 +127,15 @@ typedef struct {
  * per-domain search the paper compares against.  ens_enabled = 1: ENS with
  * buckets of n_bucket consecutive output CMPs, stage 0 (NP_f, NG_f) and
  * n_cycle backward/forward cycles (NP_bf, NG_bf); inject = 0 disables every
- * exchange between samples.  n_skip must be 0.  F, CR: fixed mutation factor
+ * exchange between samples.  n_skip (0, 1 or 2; ENS only): each stage
+ * searches every (n_skip+1)-th time sample, from offset 0 in the first
+ * forward sweep, min(1, n_skip) in backward sweeps and n_skip in later forward
+ * sweeps; the other samples take the clamped linear interpolation in t of
+ * that stage's estimates (the nearest one past either end), scored once, and
+ * in stages after the first keep their stored individual when it scores
+ * higher (sections "The performance-quality trade-off by an interpolation
+ * process" and "Evolution by neighborhood similarity", eq. for
+ * the ENS evaluation count).  F, CR: fixed mutation factor
  * and crossover rate.  polish_steps > 0: that many Adam steps of learning
  * rate polish_lr on box-normalised coordinates per winner, keeping the best
  * point.  rescore_fp64: also write the binary64 semblance of each winner,

@@ -69,7 +69,10 @@ struct ens_ctx {
     // next search issues exactly the same launches)
     struct Launch {
         ens::SearchArgs a;
+        ens::InterpArgs ia;
         int32_t kind, n_blocks, dense;
+        int32_t item_class;   // 0 first sweep, 1 backward sweeps, 2 later forward sweeps
+        int32_t interp;       // 1: interpolation of the skipped samples (ia), not a search launch
     };
     std::vector<Launch> graph_seq;
     // measured launch shapes: key -> (slices, item order)
@@ -331,7 +334,9 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
     for (int d = 0; d < P; ++d)
         if (!finite(bounds->lo[d]) || !finite(bounds->hi[d]) || !(bounds->lo[d] < bounds->hi[d]))
             return fail(ctx, ENS_E_RANGE, "ens_search: bounds %d need lo < hi", d);
-    if (de->n_skip != 0) return fail(ctx, ENS_E_RANGE, "ens_search: n_skip must be 0");
+    if (de->n_skip < 0 || de->n_skip > 2) return fail(ctx, ENS_E_RANGE, "ens_search: n_skip must be 0, 1 or 2");
+    if (de->n_skip > 0 && !de->ens_enabled)
+        return fail(ctx, ENS_E_RANGE, "ens_search: n_skip needs ens_enabled");
     if (de->ng_f < 0 || de->ng_bf < 0 || de->n_cycle < 0)
         return fail(ctx, ENS_E_RANGE, "ens_search: negative generation or cycle count");
     if (de->np_lo < 4 || de->np_hi < 4 || de->np_lo > ENS_MAX_POP || de->np_hi > ENS_MAX_POP)
@@ -359,46 +364,57 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
     // work items: consecutive t with equal NP packed floor(64/NP) per wave, in
     // (group, t) order; the second copy puts the costliest items first
     const double traces_per_cmp = static_cast<double>(ctx->n_tr) / ctx->n_cmp;
-    auto build_items = [&](int32_t n_groups, bool stage0, std::vector<int4> &items) {
+    // item classes: 0 = first sweep (NP_f), 1 = backward sweeps, 2 = later
+    // forward sweeps (NP_bf); each estimates t = t_begin + init + m stride
+    const int32_t stride = de->n_skip + 1;
+    const int32_t init_of[3] = {0, std::min(1, de->n_skip), de->n_skip};
+    auto build_items = [&](int32_t n_groups, int cls, std::vector<int4> &items) {
         for (int32_t gidx = 0; gidx < n_groups; ++gidx) {
-            int32_t t = t_begin;
+            int32_t t = t_begin + init_of[cls];
             while (t < grid->t_end) {
-                const int32_t np = stage0 ? lerp_round(de->np_lo, de->np_hi, t, nt) : de->np_bf;
+                const int32_t np = cls == 0 ? lerp_round(de->np_lo, de->np_hi, t, nt) : de->np_bf;
                 const int32_t per = ens::WAVE / np;
                 int32_t ns = 1;
-                while (ns < per && t + ns < grid->t_end &&
-                       (stage0 ? lerp_round(de->np_lo, de->np_hi, t + ns, nt) : de->np_bf) == np)
+                while (ns < per && t + ns * stride < grid->t_end &&
+                       (cls == 0 ? lerp_round(de->np_lo, de->np_hi, t + ns * stride, nt) : de->np_bf) == np)
                     ++ns;
-                items.push_back(make_int4(gidx, t, ns, np));
-                t += ns;
+                items.push_back(make_int4(gidx, t, ns | (stride << 8), np));
+                t += ns * stride;
             }
         }
     };
     auto costliest_first = [&](const std::vector<int4> &items) {
         std::vector<int4> v = items;
         auto cost = [&](const int4 &it) {
-            const int32_t tm = it.y + it.z - 1;
+            const int32_t ns = it.z & 0xff, st = it.z >> 8;
+            const int32_t tm = it.y + (ns - 1) * st;
             const int32_t ap = lerp_round(ctx->ap_lo, ctx->ap_hi, tm, nt);
-            return static_cast<double>(it.z) * it.w * (2 * ap + 1) * traces_per_cmp;
+            return static_cast<double>(ns) * it.w * (2 * ap + 1) * traces_per_cmp;
         };
         std::stable_sort(v.begin(), v.end(), [&](const int4 &x, const int4 &y) { return cost(x) > cost(y); });
         return v;
     };
     const bool ens = de->ens_enabled != 0;
     const int32_t n_buckets = ens ? (n_out + de->n_bucket - 1) / de->n_bucket : 0;
-    std::vector<int4> items0, items_bf;
-    build_items(ens ? n_buckets : n_out, true, items0);
-    if (ens && de->n_cycle > 0) build_items(n_buckets, false, items_bf);
-    const std::vector<int4> items0_lpt = costliest_first(items0), items_bf_lpt = costliest_first(items_bf);
-    // device layout: [items0 | items0 costliest-first | items_bf | items_bf costliest-first]
-    const size_t off0[3] = {0, 0, items0.size()};
-    const size_t offbf[3] = {0, 2 * items0.size(), 2 * items0.size() + items_bf.size()};
-
+    std::vector<int4> cls_items[3][3];  // [class][order 1, 2 at index 1, 2]
+    build_items(ens ? n_buckets : n_out, 0, cls_items[0][1]);
+    if (ens && de->n_cycle > 0) {
+        build_items(n_buckets, 1, cls_items[1][1]);
+        build_items(n_buckets, 2, cls_items[2][1]);
+    }
+    size_t item_off[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, n_items_total = 0;
+    for (int c = 0; c < 3; ++c) {
+        cls_items[c][2] = costliest_first(cls_items[c][1]);
+        for (int od = 1; od <= 2; ++od) {
+            item_off[c][od] = n_items_total;
+            n_items_total += cls_items[c][od].size();
+        }
+    }
     const size_t pbytes = sizeof(float) * static_cast<size_t>(n_s) * P, sbytes = sizeof(float) * n_s;
     HIP_OR_FAIL(ctx, ctx->lo_tab.ensure(lo.size() * sizeof(float)));
     HIP_OR_FAIL(ctx, ctx->hi_tab.ensure(hi.size() * sizeof(float)));
     HIP_OR_FAIL(ctx, ctx->cmp_out.ensure(cmp_out.size() * sizeof(int32_t)));
-    HIP_OR_FAIL(ctx, ctx->items.ensure(2 * (items0.size() + items_bf.size()) * sizeof(int4)));
+    HIP_OR_FAIL(ctx, ctx->items.ensure(std::max<size_t>(n_items_total, 1) * sizeof(int4)));
     HIP_OR_FAIL(ctx, ctx->counters.ensure(8 * sizeof(unsigned long long)));
     if (ens) {
         HIP_OR_FAIL(ctx, ctx->X.ensure(pbytes));
@@ -411,12 +427,11 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
     HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->cmp_out.p, cmp_out.data(), cmp_out.size() * sizeof(int32_t),
                                     hipMemcpyHostToDevice, st));
     int4 *dev_items = ctx->items.as<int4>();
-    const std::vector<int4> *parts[4] = {&items0, &items0_lpt, &items_bf, &items_bf_lpt};
-    const size_t part_off[4] = {off0[1], off0[2], offbf[1], offbf[2]};
-    for (int q = 0; q < 4; ++q)
-        if (!parts[q]->empty())
-            HIP_OR_FAIL(ctx, hipMemcpyAsync(dev_items + part_off[q], parts[q]->data(), parts[q]->size() * sizeof(int4),
-                                            hipMemcpyHostToDevice, st));
+    for (int c = 0; c < 3; ++c)
+        for (int od = 1; od <= 2; ++od)
+            if (!cls_items[c][od].empty())
+                HIP_OR_FAIL(ctx, hipMemcpyAsync(dev_items + item_off[c][od], cls_items[c][od].data(),
+                                                cls_items[c][od].size() * sizeof(int4), hipMemcpyHostToDevice, st));
 
     float *final_params = nullptr, *final_S = nullptr;
     ens::SearchArgs a{};
@@ -436,8 +451,15 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
 
     // launch sequence of the evolution (slices and item order filled in below)
     std::vector<ens_ctx::Launch> seq;
+    auto search_launch = [&](const ens::SearchArgs &sa, int kind, int cls) {
+        ens_ctx::Launch l{};
+        l.a = sa;
+        l.kind = kind;
+        l.n_blocks = static_cast<int32_t>(cls_items[cls][1].size());
+        l.item_class = cls;
+        seq.push_back(l);
+    };
     if (!ens) {
-        a.n_items = static_cast<int32_t>(items0.size());
         a.plain = 1;
         a.stage = 0;
         a.k_begin = 0;
@@ -445,7 +467,7 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
         a.ng = de->ng_f;
         a.Yp = out->params;
         a.YS = out->S;
-        seq.push_back({a, 0, a.n_items, 0});
+        search_launch(a, 0, 0);
     } else {
         float *X = ctx->X.as<float>(), *XS = ctx->XS.as<float>();
         float *Y = ctx->Y.as<float>(), *YS = ctx->YS.as<float>();
@@ -455,10 +477,11 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
         constexpr int32_t STEPS = 32;
         const int32_t n_steps = std::min(de->n_bucket, n_out);
         for (int32_t s = 0; s < n_stage; ++s) {
+            const int cls = s == 0 ? 0 : (s % 2 == 1 ? 1 : 2);
             a.stage = s;
             a.forward = (s % 2 == 0) ? 1 : 0;
             a.ng = s == 0 ? de->ng_f : de->ng_bf;
-            a.n_items = static_cast<int32_t>(s == 0 ? items0.size() : items_bf.size());
+            a.n_items = static_cast<int32_t>(cls_items[cls][1].size());
             a.Xp = X;
             a.XS = XS;
             a.Yp = Y;
@@ -466,7 +489,31 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
             for (int32_t k0 = 0; k0 < n_steps; k0 += STEPS) {
                 a.k_begin = k0;
                 a.k_end = std::min(n_steps, k0 + STEPS);
-                seq.push_back({a, s == 0 ? 0 : 1, a.n_items, 0});
+                search_launch(a, s == 0 ? 0 : 1, cls);
+            }
+            if (stride > 1) {
+                ens_ctx::Launch l{};
+                l.interp = 1;
+                l.kind = s == 0 ? 0 : 1;
+                l.item_class = cls;
+                ens::InterpArgs &ia = l.ia;
+                ia.sv = a.sv;
+                ia.cmp_out = a.cmp_out;
+                ia.n_out = n_out;
+                ia.t_begin = t_begin;
+                ia.n_t = n_t;
+                ia.lo_tab = a.lo_tab;
+                ia.hi_tab = a.hi_tab;
+                ia.stride = stride;
+                ia.init = init_of[cls];
+                ia.stage = s;
+                ia.kind = l.kind;
+                ia.Xp = X;
+                ia.XS = XS;
+                ia.Yp = Y;
+                ia.YS = YS;
+                ia.counters = ctx->counters.as<unsigned long long>();
+                seq.push_back(l);
             }
             std::swap(X, Y);
             std::swap(XS, YS);
@@ -481,14 +528,14 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
     for (int kind = 0; kind < 2; ++kind) {
         const ens_ctx::Launch *first = nullptr;
         for (const auto &l : seq)
-            if (l.kind == kind) {
+            if (l.kind == kind && !l.interp) {
                 first = &l;
                 break;
             }
         if (!first) continue;
         char key[256];
-        snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d", kind, P, ctx->store_dtype, ctx->window,
-                 de->np_lo, de->np_hi, first->a.ng, first->n_blocks, n_out, n_t, ctx->ap_hi);
+        snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d", kind, P, ctx->store_dtype, ctx->window,
+                 de->np_lo, de->np_hi, first->a.ng, first->n_blocks, n_out, n_t, ctx->ap_hi, stride);
         int nsl = ctx->tuning.waves_per_sample_group, order = ctx->tuning.item_order;
         int dense = ctx->tuning.occupancy == 0 ? -1 : (ctx->tuning.occupancy == 2 ? 1 : 0);
         if (nsl == 0 || order == 0 || dense < 0) {
@@ -523,14 +570,14 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
             for (int warm = 0; warm <= 1; ++warm) {  // load both kernel variants once
                 ta.nsl = cands[0].nsl;
                 ta.xcd_order = 1;
-                ta.items = dev_items + (kind == 0 ? off0[1] : offbf[1]);
+                ta.items = dev_items + item_off[first->item_class][1];
                 HIP_OR_FAIL(ctx, ens::launch_search(P, ctx->store_dtype, ctx->window, kind, warm, ta,
                                                     first->n_blocks, st));
             }
             for (size_t c = 0; c < cands.size(); ++c) {
                 ta.nsl = cands[c].nsl;
                 ta.xcd_order = cands[c].order == 1;
-                ta.items = dev_items + (kind == 0 ? off0[cands[c].order] : offbf[cands[c].order]);
+                ta.items = dev_items + item_off[first->item_class][cands[c].order];
                 HIP_OR_FAIL(ctx, hipEventRecord(ctx->events[2 * c], st));
                 HIP_OR_FAIL(ctx, ens::launch_search(P, ctx->store_dtype, ctx->window, kind, cands[c].dense, ta,
                                                     first->n_blocks, st));
@@ -555,10 +602,10 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
         ctx->stats.order_used[kind] = order;
         ctx->stats.dense_used[kind] = dense;
         for (auto &l : seq)
-            if (l.kind == kind) {
+            if (l.kind == kind && !l.interp) {
                 l.a.nsl = nsl;
                 l.a.xcd_order = order == 1;
-                l.a.items = dev_items + (kind == 0 ? off0[order] : offbf[order]);
+                l.a.items = dev_items + item_off[l.item_class][order];
                 l.dense = dense;
             }
     }
@@ -582,7 +629,8 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
             HIP_OR_FAIL(ctx, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
             hipError_t le = hipSuccess;
             for (const auto &l : seq) {
-                le = ens::launch_search(P, ctx->store_dtype, ctx->window, l.kind, l.dense, l.a, l.n_blocks, st);
+                le = l.interp ? ens::launch_interp(P, ctx->store_dtype, ctx->window, l.ia, st)
+                              : ens::launch_search(P, ctx->store_dtype, ctx->window, l.kind, l.dense, l.a, l.n_blocks, st);
                 if (le != hipSuccess) break;
             }
             hipGraph_t gph = nullptr;
@@ -598,7 +646,10 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
         for (size_t i = 0; i < seq.size(); ++i) {
             const auto &l = seq[i];
             if (timing) HIP_OR_FAIL(ctx, hipEventRecord(ctx->events[2 * i], st));
-            HIP_OR_FAIL(ctx, ens::launch_search(P, ctx->store_dtype, ctx->window, l.kind, l.dense, l.a, l.n_blocks, st));
+            if (l.interp)
+                HIP_OR_FAIL(ctx, ens::launch_interp(P, ctx->store_dtype, ctx->window, l.ia, st));
+            else
+                HIP_OR_FAIL(ctx, ens::launch_search(P, ctx->store_dtype, ctx->window, l.kind, l.dense, l.a, l.n_blocks, st));
             if (timing) HIP_OR_FAIL(ctx, hipEventRecord(ctx->events[2 * i + 1], st));
         }
     }

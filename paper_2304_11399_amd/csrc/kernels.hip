@@ -404,12 +404,13 @@ __device__ __forceinline__ void search_body(const SearchArgs &a)
         k_begin = a.k_begin;
         k_end = min(a.k_end, nb);
     }
-    const int32_t t_start = it.y, ns = it.z, np = it.w;
+    // item: t_start, ns samples t_start + m stride (stride in bits 8..15), NP
+    const int32_t t_start = it.y, ns = it.z & 0xff, stride = it.z >> 8, np = it.w;
     const int32_t grp = lane / np;
     const bool live = grp < ns;
     const int32_t slot = lane - grp * np;
     const int32_t base = grp * np;
-    const int32_t n0 = t_start + (live ? grp : ns - 1);
+    const int32_t n0 = t_start + (live ? grp : ns - 1) * stride;
     const int32_t tt = n0 - a.t_begin;
     const int32_t ap = a.sv.ap_tab[n0];
     float lo[3] = {0.f, 0.f, 0.f}, hi[3] = {0.f, 0.f, 0.f};
@@ -419,7 +420,7 @@ __device__ __forceinline__ void search_body(const SearchArgs &a)
         hi[d] = a.hi_tab[n0 * 3 + d];
     }
     // apertures grow or shrink linearly in t: the item's extreme samples bound them
-    const int32_t amax = max(a.sv.ap_tab[t_start], a.sv.ap_tab[t_start + ns - 1]);
+    const int32_t amax = max(a.sv.ap_tab[t_start], a.sv.ap_tab[t_start + (ns - 1) * stride]);
     const uint64_t stage = static_cast<uint64_t>(a.stage);
     int buf = 0;
     int32_t M = 0;
@@ -511,6 +512,83 @@ __device__ __forceinline__ void search_body(const SearchArgs &a)
             atomicAdd(a.counters + 2 * KIND, static_cast<unsigned long long>(tot_ev));
             atomicAdd(a.counters + 2 * KIND + 1, static_cast<unsigned long long>(tot_m));
         }
+    }
+}
+
+// Time-sample skipping: after a stage, every sample it did not estimate
+// takes the parameters interpolated linearly in t between the nearest
+// estimated samples of the stage on the same trace (the nearest one alone at
+// the grid ends), clamped into its box, and is scored once; from the second
+// stage on the interpolated individual replaces the stored one only when it
+// scores higher (section "The performance-quality trade-off by an
+// interpolation process").  Lane = (output CMP, time sample).
+template <int OP, int DT, int W>
+__global__ __launch_bounds__(256) void k_interp(InterpArgs a)
+{
+    const int64_t total = static_cast<int64_t>(a.n_out) * a.n_t;
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const bool in_grid = c < total;
+    const int64_t cc = in_grid ? c : total - 1;
+    const int32_t o = static_cast<int32_t>(cc / a.n_t);
+    const int32_t tt = static_cast<int32_t>(cc - static_cast<int64_t>(o) * a.n_t);
+    const int32_t stride = a.stride, init = a.init;
+    const bool estimated = tt >= init && (tt - init) % stride == 0;
+    const int32_t ta = tt > init ? tt - (tt - init) % stride : -1;
+    const int32_t tb_ = tt < init ? init : tt - (tt - init) % stride + stride;
+    const int32_t tb = tb_ < a.n_t ? tb_ : -1;
+    const bool has = ta >= 0 || tb >= 0;
+    const bool live = in_grid && !estimated;
+    const int32_t n0 = a.t_begin + tt;
+    const int32_t j = a.cmp_out[o];
+    const int32_t ap = a.sv.ap_tab[n0];
+    const int64_t row = static_cast<int64_t>(o) * a.n_t;
+    float p[3] = {0.f, 0.f, 0.f};
+    if (has) {
+        const float *pa = a.Yp + (row + (ta >= 0 ? ta : tb)) * OP;
+        const float *pb = a.Yp + (row + (tb >= 0 ? tb : ta)) * OP;
+        if (ta >= 0 && tb >= 0) {
+            const float wgt = static_cast<float>(tt - ta) / static_cast<float>(tb - ta);
+#pragma unroll
+            for (int d = 0; d < OP; ++d) {
+                const float diff = pb[d] - pa[d];
+                const float step = wgt * diff;
+                p[d] = pa[d] + step;
+            }
+        } else {
+#pragma unroll
+            for (int d = 0; d < OP; ++d) p[d] = pa[d];
+        }
+#pragma unroll
+        for (int d = 0; d < OP; ++d) {
+            p[d] = fmaxf(p[d], a.lo_tab[n0 * 3 + d]);
+            p[d] = fminf(p[d], a.hi_tab[n0 * 3 + d]);
+        }
+    }
+    const Cand<float> cand = make_cand<OP, float>(p, n0, j, ap, a.sv.nt, a.sv.dt, a.sv.dx);
+    int32_t c_lo, c_hi;
+    wave_cmp_range(a.sv, j, ap, live && has, c_lo, c_hi);
+    Acc<W, float> acc;
+    acc.reset();
+    accumulate_range<DT, W, float>(a.sv, cand, c_lo, c_hi, 0, 1, acc);
+    const float Sp = finish_semblance(acc);
+    const bool counted = live && has;
+    if (live) {
+        const int64_t here = row + tt;
+        if (has && (a.stage == 0 || Sp > a.XS[here])) {
+#pragma unroll
+            for (int d = 0; d < OP; ++d) a.Yp[here * OP + d] = p[d];
+            a.YS[here] = Sp;
+        } else if (a.stage > 0) {
+#pragma unroll
+            for (int d = 0; d < OP; ++d) a.Yp[here * OP + d] = a.Xp[here * OP + d];
+            a.YS[here] = a.XS[here];
+        }
+    }
+    const uint64_t n = wave_sum(static_cast<uint64_t>(counted ? 1 : 0));
+    const uint64_t m = wave_sum(static_cast<uint64_t>(counted ? acc.M : 0));
+    if ((threadIdx.x & (WAVE - 1)) == 0) {
+        atomicAdd(a.counters + 2 * a.kind, static_cast<unsigned long long>(n));
+        atomicAdd(a.counters + 2 * a.kind + 1, static_cast<unsigned long long>(m));
     }
 }
 
@@ -759,6 +837,15 @@ hipError_t launch_search(int op, int dtype, int window, int kind, int dense, con
         ENS_DISPATCH_OP(op, ENS_DISPATCH_DT(dtype, ENS_DISPATCH_W(window,
             hipLaunchKernelGGL((k_search_dense<OP, DT, W, 1>), grid, block, lds, s, a))));
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_interp(int op, int dtype, int window, const InterpArgs &a, hipStream_t s)
+{
+    const int64_t total = static_cast<int64_t>(a.n_out) * a.n_t;
+    if (total == 0) return hipSuccess;
+    ENS_DISPATCH_OP(op, ENS_DISPATCH_DT(dtype, ENS_DISPATCH_W(window,
+        hipLaunchKernelGGL((k_interp<OP, DT, W>), dim3(blocks_for(total, 256)), dim3(256), 0, s, a))));
     return hipGetLastError();
 }
 

@@ -36,7 +36,8 @@ struct SearchArgs {
     const int32_t *cmp_out;   // [n_out] output CMPs
     int32_t n_out, t_begin, n_t;
     const float *lo_tab, *hi_tab;  // [nt][3] per-time boxes
-    const int4 *items;        // work items {output index or bucket, first t, samples, NP}
+    const int4 *items;        // work items {output index or bucket, first t,
+                              //  samples | stride << 8, NP}
     int32_t n_items;
     int32_t plain, stage, k_begin, k_end, forward, n_bucket, ng, inject, nsl;
     int32_t xcd_order;        // 1: deal consecutive items to one XCD; 0: items in block order
@@ -46,6 +47,18 @@ struct SearchArgs {
     const float *Xp, *XS;     // previous stage state [n_out][n_t][P], [n_out][n_t]
     float *Yp, *YS;           // this stage's state
     unsigned long long *counters;  // [2 KIND] evaluations, [2 KIND + 1] participating traces
+};
+
+// Interpolation of the samples a stage skipped (time-sample skipping).
+struct InterpArgs {
+    StoreView sv;
+    const int32_t *cmp_out;
+    int32_t n_out, t_begin, n_t;
+    const float *lo_tab, *hi_tab;
+    int32_t stride, init, stage, kind;
+    const float *Xp, *XS;     // previous stage state (stage > 0)
+    float *Yp, *YS;           // this stage's state, in/out
+    unsigned long long *counters;
 };
 
 struct PolishArgs {
@@ -79,6 +92,7 @@ hipError_t launch_backward(int op, int dtype, int window, const StoreView &sv, c
 hipError_t launch_search(int op, int dtype, int window, int kind, int dense, const SearchArgs &a,
                          int32_t n_blocks, hipStream_t s);
 hipError_t launch_polish(int op, int dtype, int window, const PolishArgs &a, hipStream_t s);
+hipError_t launch_interp(int op, int dtype, int window, const InterpArgs &a, hipStream_t s);
 hipError_t launch_philox(int64_t n, const uint64_t *ctr, const uint64_t *key, uint64_t *out,
                          hipStream_t s);
 hipError_t launch_de_trial(int32_t n_pop, int32_t np, int32_t P, const float *pop, const float *S,
