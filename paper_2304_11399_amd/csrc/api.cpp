@@ -61,7 +61,7 @@ struct ens_ctx {
     int32_t op = 0, window = 0, ap_lo = 0, ap_hi = 0;
     DevBuf store, master, scale, meta, cmp_ptr, ap_tab;
     // search workspace
-    DevBuf lo_tab, hi_tab, items, X, XS, Y, YS, counters, cmp_out, flag;
+    DevBuf lo_tab, hi_tab, items, X, XS, Y, YS, counters, cmp_out, flag, progress;
     // statistics of the last search, launch timing events
     ens_stats stats{};
     std::vector<hipEvent_t> events;
@@ -95,7 +95,7 @@ struct ens_ctx {
         drop_graph();
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
         for (DevBuf *b : {&store, &master, &scale, &meta, &cmp_ptr, &ap_tab, &lo_tab, &hi_tab, &items,
-                          &X, &XS, &Y, &YS, &counters, &cmp_out, &flag})
+                          &X, &XS, &Y, &YS, &counters, &cmp_out, &flag, &progress})
             b->release();
     }
 };
@@ -521,6 +521,17 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
         final_params = X;
         final_S = XS;
     }
+    // one step counter per ENS search launch (pacing), plus one for shape trials
+    size_t n_paced = 0;
+    for (const auto &l : seq)
+        if (!l.interp && !l.a.plain) ++n_paced;
+    HIP_OR_FAIL(ctx, ctx->progress.ensure((n_paced + 1) * sizeof(unsigned long long)));
+    unsigned long long *const progress = ctx->progress.as<unsigned long long>();
+    {
+        size_t i = 0;
+        for (auto &l : seq)
+            if (!l.interp && !l.a.plain) l.a.progress = progress + i++;
+    }
     ctx->stats = ens_stats{};
     ctx->stats.struct_size = sizeof(ens_stats);
 
@@ -567,7 +578,9 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
                 HIP_OR_FAIL(ctx, hipEventCreate(&e));
                 ctx->events.push_back(e);
             }
+            if (ta.progress) ta.progress = progress + n_paced;
             for (int warm = 0; warm <= 1; ++warm) {  // load both kernel variants once
+                if (ta.progress) HIP_OR_FAIL(ctx, hipMemsetAsync(ta.progress, 0, sizeof(unsigned long long), st));
                 ta.nsl = cands[0].nsl;
                 ta.xcd_order = 1;
                 ta.items = dev_items + item_off[first->item_class][1];
@@ -578,6 +591,7 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
                 ta.nsl = cands[c].nsl;
                 ta.xcd_order = cands[c].order == 1;
                 ta.items = dev_items + item_off[first->item_class][cands[c].order];
+                if (ta.progress) HIP_OR_FAIL(ctx, hipMemsetAsync(ta.progress, 0, sizeof(unsigned long long), st));
                 HIP_OR_FAIL(ctx, hipEventRecord(ctx->events[2 * c], st));
                 HIP_OR_FAIL(ctx, ens::launch_search(P, ctx->store_dtype, ctx->window, kind, cands[c].dense, ta,
                                                     first->n_blocks, st));
@@ -610,6 +624,7 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
             }
     }
     HIP_OR_FAIL(ctx, hipMemsetAsync(ctx->counters.p, 0, 8 * sizeof(unsigned long long), st));
+    HIP_OR_FAIL(ctx, hipMemsetAsync(progress, 0, (n_paced + 1) * sizeof(unsigned long long), st));
     for (const auto &l : seq) ctx->stats.launches[l.kind] += 1;
     const bool timing = ctx->tuning.collect_timing != 0;
     const bool graph = ctx->tuning.use_graph != 0 && !timing;

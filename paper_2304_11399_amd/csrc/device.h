@@ -118,6 +118,17 @@ __device__ __forceinline__ void load_window(const typename Store<DT>::T *__restr
     }
 }
 
+// The per-line tables (CMP offsets, trace geometry, scales) stay unchanged
+// while a kernel runs: read through the constant address space, their
+// wave-uniform reads become scalar loads, which do not wait behind the
+// vector memory pipe.
+#define ENS_CONST_AS __attribute__((address_space(4)))
+template <typename T>
+__device__ __forceinline__ const ENS_CONST_AS T *const_view(const T *p)
+{
+    return (const ENS_CONST_AS T *)(p);
+}
+
 // Per-trace geometry, one 16-byte record per trace.
 struct TraceMeta {
     float cx;      // CMP position c * dx

@@ -107,12 +107,14 @@ __device__ __forceinline__ void wave_cmp_range(const StoreView &sv, int32_t j, i
 }
 
 template <typename R>
-__device__ __forceinline__ R h2_of(const TraceMeta &tm)
+__device__ __forceinline__ R h2_of(const ENS_CONST_AS TraceMeta *meta, int32_t i)
 {
-    if constexpr (sizeof(R) == 8)
-        return static_cast<R>(tm.h) * static_cast<R>(tm.h);
-    else
-        return tm.h2;
+    if constexpr (sizeof(R) == 8) {
+        const R h = static_cast<R>(meta[i].h);
+        return h * h;
+    } else {
+        return meta[i].h2;
+    }
 }
 
 // Window sums of one candidate over the traces of CMPs c_lo..c_hi; in each
@@ -125,24 +127,27 @@ __device__ __forceinline__ void accumulate_cmps(const StoreView &sv, const Cand<
 {
     using T = typename Store<DT>::T;
     const T *store = static_cast<const T *>(sv.store);
+    const ENS_CONST_AS int64_t *cmp_ptr = const_view(sv.cmp_ptr);
+    const ENS_CONST_AS TraceMeta *meta = const_view(sv.meta);
+    const ENS_CONST_AS float *scale = const_view(sv.scale);
     const R dx = static_cast<R>(sv.dx);
     for (int32_t c = c_lo; c <= c_hi; ++c) {
         const CmpTerm<R> ct = cmp_term(cand, c, dx);
-        const int32_t i1 = static_cast<int32_t>(sv.cmp_ptr[c + 1]);
-        int32_t i = static_cast<int32_t>(sv.cmp_ptr[c]) + first;
+        const int32_t i1 = static_cast<int32_t>(cmp_ptr[c + 1]);
+        int32_t i = static_cast<int32_t>(cmp_ptr[c]) + first;
         for (; i + step < i1; i += 2 * step) {
             const int32_t i2 = i + step;
-            accum_trace<DT, W, SCALED>(acc, cand, ct, h2_of<R>(sv.meta[i]),
+            accum_trace<DT, W, SCALED>(acc, cand, ct, h2_of<R>(meta, i),
                                        store + static_cast<size_t>(i) * sv.ld,
-                                       SCALED ? sv.scale[i] : 1.0f);
-            accum_trace<DT, W, SCALED>(acc, cand, ct, h2_of<R>(sv.meta[i2]),
+                                       SCALED ? scale[i] : 1.0f);
+            accum_trace<DT, W, SCALED>(acc, cand, ct, h2_of<R>(meta, i2),
                                        store + static_cast<size_t>(i2) * sv.ld,
-                                       SCALED ? sv.scale[i2] : 1.0f);
+                                       SCALED ? scale[i2] : 1.0f);
         }
         if (i < i1)
-            accum_trace<DT, W, SCALED>(acc, cand, ct, h2_of<R>(sv.meta[i]),
+            accum_trace<DT, W, SCALED>(acc, cand, ct, h2_of<R>(meta, i),
                                        store + static_cast<size_t>(i) * sv.ld,
-                                       SCALED ? sv.scale[i] : 1.0f);
+                                       SCALED ? scale[i] : 1.0f);
     }
 }
 
@@ -235,14 +240,17 @@ __device__ __forceinline__ float semblance_grad_lane(const StoreView &sv, const 
     const float coef = nonzero ? 2.0f / (static_cast<float>(acc.M) * acc.E) : 0.0f;
     const float MS = static_cast<float>(acc.M) * S;
     const float inv_dt = 1.0f / sv.dt;
+    const ENS_CONST_AS int64_t *cmp_ptr = const_view(sv.cmp_ptr);
+    const ENS_CONST_AS TraceMeta *meta = const_view(sv.meta);
+    const ENS_CONST_AS float *scale = const_view(sv.scale);
     for (int32_t c = c_lo; c <= c_hi; ++c) {
         const CmpTerm<float> ct = cmp_term(cand, c, sv.dx);
-        const int32_t i1 = static_cast<int32_t>(sv.cmp_ptr[c + 1]);
-        for (int32_t i = static_cast<int32_t>(sv.cmp_ptr[c]); i < i1; ++i) {
-            const float h2 = sv.meta[i].h2;
+        const int32_t i1 = static_cast<int32_t>(cmp_ptr[c + 1]);
+        for (int32_t i = static_cast<int32_t>(cmp_ptr[c]); i < i1; ++i) {
+            const float h2 = meta[i].h2;
             const TT<float> tt = traveltime<W>(cand, ct, h2);
             const bool use = nonzero && tt.ok && tt.tau > 0.0f;
-            const float sc = sv.scale ? sv.scale[i] : 1.0f;
+            const float sc = scale ? scale[i] : 1.0f;
             float u[W + 1];
             load_window<DT, W + 1>(store + static_cast<size_t>(i) * sv.ld, tt.off, u);
             const float wa = (1.0f - tt.f) * sc, wb = tt.f * sc;
@@ -377,6 +385,28 @@ __device__ __forceinline__ float eval_slices(const StoreView &sv, const Cand<flo
 
 // Evolution of a group of samples: lane = (sample, slot), floor(64/NP)
 // samples of one output CMP per wave, the trace loop split over nsl waves.
+// Sweep pacing.  Every workgroup of an ENS launch sweeps the same number of
+// trace steps and all of them are resident together, so the launch lasts as
+// long as its slowest sweep.  The wave arbiter favours older waves, which lets
+// the first-dispatched sweeps race ahead and leaves the last ones to finish
+// alone on a half-empty chip.  Before each step a wave compares its progress
+// with the launch's mean (steps counts every finished step of every
+// workgroup) and takes a high issue priority when behind, a low one when
+// ahead; the results do not depend on it.
+__device__ __forceinline__ void pace_by_progress(const unsigned long long *steps, int32_t done_here)
+{
+    const unsigned long long all = __hip_atomic_load(steps, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int64_t total = static_cast<int64_t>(__builtin_amdgcn_readfirstlane(static_cast<uint32_t>(all)));
+    const int64_t mine = static_cast<int64_t>(done_here) * gridDim.x;
+    const int64_t half = gridDim.x / 2;
+    if (mine + half < total)
+        __builtin_amdgcn_s_setprio(3);
+    else if (mine > total + half)
+        __builtin_amdgcn_s_setprio(0);
+    else
+        __builtin_amdgcn_s_setprio(1);
+}
+
 // Plain search: each workgroup runs the whole evolution (initial population
 // and NG generations) of its samples.  ENS: each workgroup sweeps its time
 // samples through the traces of its bucket, one trace after another: within
@@ -429,6 +459,7 @@ __device__ __forceinline__ void search_body(const SearchArgs &a)
     float pbest[3] = {0.f, 0.f, 0.f};  // this sample's best on the previous trace of the sweep
 
     for (int32_t k = k_begin; k < k_end; ++k) {
+        if (a.progress) pace_by_progress(a.progress, k - k_begin);
         const int32_t o = a.plain ? it.x : b0 + (a.forward ? k : nb - 1 - k);
         const int32_t prev = k > 0 ? (a.forward ? o - 1 : o + 1) : -1;
         const int32_t j = __builtin_amdgcn_readfirstlane(a.cmp_out[o]);
@@ -459,7 +490,8 @@ __device__ __forceinline__ void search_body(const SearchArgs &a)
             }
             if (a.stage > 0) {
                 if (a.inject && slot == 0 && tt > 0) load_clamped<OP>(a.Xp + (here - 1) * OP, lo, hi, x);
-                if (a.inject && slot == 1 && tt < a.n_t - 1) load_clamped<OP>(a.Xp + (here + 1) * OP, lo, hi, x);
+                if (a.inject && slot == 1 && tt < a.n_t - 1)
+                    load_clamped<OP>(a.Xp + (here + 1) * OP, lo, hi, x);
                 if (slot == 3) {
 #pragma unroll
                     for (int d = 0; d < OP; ++d) x[d] = a.Xp[here * OP + d];
@@ -481,7 +513,8 @@ __device__ __forceinline__ void search_body(const SearchArgs &a)
         }
         // generations (sections "Mutation and crossover", "Selection")
         for (int32_t g = 1; g <= a.ng; ++g) {
-            philox4x64_10(sid, stage, static_cast<uint64_t>(g), static_cast<uint64_t>(slot), a.seed, 0, w);
+            philox4x64_10(sid, stage, static_cast<uint64_t>(g), static_cast<uint64_t>(slot), a.seed, 0,
+                          w);
             float u[3] = {0.f, 0.f, 0.f};
             make_trial<OP>(x, S, base, np, slot, w, a.F, a.cr_thr, lo, hi, u);
             const Cand<float> cand = make_cand<OP, float>(u, n0, j, ap, a.sv.nt, a.sv.dt, a.sv.dx);
@@ -504,6 +537,7 @@ __device__ __forceinline__ void search_body(const SearchArgs &a)
             for (int d = 0; d < OP; ++d) a.Yp[here * OP + d] = x[d];
             a.YS[here] = S;
         }
+        if (a.progress && threadIdx.x == 0) atomicAdd(a.progress, 1ull);
     }
     if (wave == 0) {
         const uint64_t tot_ev = wave_sum(static_cast<uint64_t>(n_ev));

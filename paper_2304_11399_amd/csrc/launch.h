@@ -47,6 +47,7 @@ struct SearchArgs {
     const float *Xp, *XS;     // previous stage state [n_out][n_t][P], [n_out][n_t]
     float *Yp, *YS;           // this stage's state
     unsigned long long *counters;  // [2 KIND] evaluations, [2 KIND + 1] participating traces
+    unsigned long long *progress;  // sweep steps finished in this launch (zeroed before it), or null
 };
 
 // Interpolation of the samples a stage skipped (time-sample skipping).

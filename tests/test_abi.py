@@ -44,6 +44,27 @@ def test_struct_sizes_match_header_layout():
     assert C.sizeof(ens.Tuning) == 24
 
 
+def test_struct_sizes_match_the_c_compiler(tmp_path):
+    # the header compiled by the host C compiler gives the same sizes
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    names = ["ens_traces", "ens_de_cfg", "ens_result", "ens_stats", "ens_tuning",
+             "ens_geometry", "ens_sem_cfg", "ens_t0_grid", "ens_bounds", "ens_candidates"]
+    src = tmp_path / "sizes.c"
+    src.write_text('#include <stdio.h>\n#include "ens.h"\nint main(void){\n' +
+                   "".join(f'printf("%zu\\n", sizeof({n}));\n' for n in names) + "return 0;}\n")
+    exe = tmp_path / "sizes"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    mirrors = [ens.Traces, ens.DeCfg, ens.Result, ens.Stats, ens.Tuning, ens.Geometry, ens.SemCfg,
+               ens.T0Grid, ens.Bounds, ens.Candidates]
+    assert got == [C.sizeof(m) for m in mirrors]
+
+
 def test_null_and_state_errors():
     lib, h = _ctx()
     try:
@@ -103,7 +124,7 @@ def test_bind_rejects_bad_geometry_and_struct_size():
 def test_tuning_and_building_block_validation():
     lib, h = _ctx()
     try:
-        t = ens._sized(ens.Tuning, waves_per_sample_group=3)
+        t = ens._sized(ens.Tuning, waves_per_sample_group=9)
         assert lib.ens_set_tuning(h, C.byref(t)) == -2
         t.waves_per_sample_group = 4
         assert lib.ens_set_tuning(h, C.byref(t)) == 0
