@@ -228,9 +228,9 @@ __device__ __forceinline__ CmpTerm<R> cmp_term(const Cand<R> &cand, int32_t c, R
     return t;
 }
 
-// Traveltime of (candidate, trace) in sample units.  q = n0^2 + mo < 0 gives
-// dtau < -n0 (tau clamps to 0, dtau = mo / n0) and so fails the range test,
-// as does any trace outside the candidate's aperture.  off: column of the
+// Traveltime of (candidate, trace) in sample units.  q = n0^2 + mo < 0 (no
+// real traveltime) fails the range test, as does any trace outside the
+// candidate's aperture.  off: column of the
 // window's first sample in the padded row, or 0 (a run of zero padding) for
 // a trace that does not take part.
 template <typename R>
@@ -247,7 +247,9 @@ __device__ __forceinline__ TT<R> traveltime(const Cand<R> &c, const CmpTerm<R> &
     TT<R> r;
     const R mo = fmadd(c.ga, h2, ct.part);
     const R q = c.n0sq + mo;
-    const R tau = fast_sqrt(q > R(0) ? q : R(0));
+    // q < 0: the square root is NaN, the guarded denominator 1e-30 and the
+    // clamped dtau -1e30 (mo < -n0^2 <= 0), below every range
+    const R tau = fast_sqrt(q);
     const R s = tau + c.n0f;
     const R den = s > R(1e-30) ? s : R(1e-30);
     const R dtau = clamp_big(mo * fast_rcp(den));
@@ -278,9 +280,14 @@ __device__ __forceinline__ void accum_trace(Acc<W, R> &acc, const Cand<R> &c, co
     load_window<DT, W + 1>(row, tt.off, u);
 #pragma unroll
     for (int k = 0; k < W; ++k) {
-        // written as two fused steps so that binary16 samples feed the
-        // mixed-precision FMA without a separate conversion
-        const R a = fmadd(wb, static_cast<R>(u[k + 1]), fmadd(wa, static_cast<R>(u[k]), R(0)));
+        // binary16 samples: two fused steps, so that they feed the
+        // mixed-precision FMA without a separate conversion; binary32: a
+        // product and one fused step (same value)
+        R a;
+        if constexpr (DT == DT_F32)
+            a = fmadd(wb, static_cast<R>(u[k + 1]), wa * static_cast<R>(u[k]));
+        else
+            a = fmadd(wb, static_cast<R>(u[k + 1]), fmadd(wa, static_cast<R>(u[k]), R(0)));
         acc.s[k] += a;
         acc.E = fmadd(a, a, acc.E);
     }
