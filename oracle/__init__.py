@@ -14,7 +14,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
-SOURCES = ["philox.c", "semblance.c", "search.c", "refine.c", "quant.c"]
+SOURCES = ["philox.c", "semblance.c", "search.c", "refine.c", "quant.c", "stack.c"]
 
 _lib = None
 
@@ -79,6 +79,9 @@ def lib():
         L.or_bf16_to_double.restype = C.c_double
         L.or_sref.argtypes = [C.POINTER(_Line), C.POINTER(_Bounds), C.c_int64, P, P, P,
                               C.c_int32, P, P]
+        L.or_stack_batch.argtypes = [C.POINTER(_Line), C.c_int64, P, P, P, P, P]
+        L.or_rms.argtypes = [P, C.c_int64]
+        L.or_rms.restype = C.c_double
         _lib = L
     return _lib
 
@@ -139,6 +142,17 @@ class Line:
         lib().or_semblance_batch(C.byref(self._s), n, _ptr(cmp), _ptr(t), _ptr(p), _ptr(S),
                                  _ptr(M), _ptr(mg))
         return S, M, mg
+
+    def stack(self, cmp, t, params):
+        """Zero-offset stack (float64) and participating traces M per sample."""
+        cmp = np.ascontiguousarray(cmp, dtype=np.int32)
+        t = np.ascontiguousarray(t, dtype=np.int32)
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(-1, self.op))
+        n = cmp.size
+        out = np.zeros(n)
+        M = np.zeros(n, np.int32)
+        lib().or_stack_batch(C.byref(self._s), n, _ptr(cmp), _ptr(t), _ptr(p), _ptr(out), _ptr(M))
+        return out, M
 
     def semblance_grad(self, cmp, t, params):
         cmp = np.ascontiguousarray(cmp, dtype=np.int32)
@@ -228,6 +242,12 @@ def de_trial(pop, S, words, F, CR, lo, hi):
     lib().or_de_trial(npop, P, _ptr(pop), _ptr(S), _ptr(words), float(F), float(CR), _ptr(lo),
                       _ptr(hi), _ptr(out))
     return out
+
+
+def rms(x):
+    """Root mean square of a panel (binary64)."""
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1)
+    return float(lib().or_rms(_ptr(x), x.size))
 
 
 def quantize(u, dtype):

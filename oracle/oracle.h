@@ -100,6 +100,14 @@ void or_quantize(const float *u, int64_t n_tr, int32_t nt, int32_t dtype /*1 f16
 double or_half_to_double(uint16_t h);
 double or_bf16_to_double(uint16_t h);
 
+/* Zero-offset stack: mean over the participating traces of the interpolated
+ * amplitude at each trace's traveltime (0 when none takes part). */
+double or_stack(const or_line *L, int32_t j, int32_t n0, const double *p, int32_t *M_out);
+void or_stack_batch(const or_line *L, int64_t n, const int32_t *cmp, const int32_t *t,
+                    const double *params, double *out, int32_t *M);
+/* Root mean square of a panel. */
+double or_rms(const double *x, int64_t n);
+
 /* Reference maximum of S per sample: uniform grid then local refinement. */
 void or_sref(const or_line *L, const or_bounds *B, int64_t n, const int32_t *cmp,
              const int32_t *t, const int32_t *grid /*[3] points per axis*/, int32_t n_refine,
