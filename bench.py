@@ -222,6 +222,14 @@ def main():
         st = ctx.stats()
         ctx.set_tuning(waves_per_sample_group=args.waves, item_order=args.order,
                        occupancy=args.occupancy)
+        # quality outputs of the last step, outside the timed region: the
+        # zero-offset stack along the winners and the coherence-panel RMS
+        torch.cuda.synchronize()
+        t_st = time.perf_counter()
+        stack, coherence_rms = ctx.stack(out["params"], out["S"])
+        stack_ms = 1e3 * (time.perf_counter() - t_st)
+        stack_info = {"ms": round(stack_ms, 3), "coherence_rms": round(coherence_rms, 6),
+                      "stack_rms": round(float(stack.double().pow(2).mean().sqrt().item()), 6)}
         comparison = None
         if not args.no_compare and not args.no_gap:
             comparison = compare_equal_accuracy(
@@ -280,6 +288,7 @@ def main():
         "gap_ok": None if not gap or "mean" not in gap else bool(gap["mean"] <= 1e-3),
         "roofline": roof,
         "stats": st,
+        "stack": stack_info,
         "equal_accuracy": comparison,
     }
     if not args.no_cpu_baseline:

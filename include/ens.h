@@ -261,6 +261,21 @@ ens_status semblance_eval64(ens_ctx *ctx, const ens_candidates *cands, double *S
 ens_status semblance_backward(ens_ctx *ctx, const ens_candidates *cands, const float *dS,
                               float *dparams_out);
 
+/* ---- outputs for inspection --------------------------------------------- */
+
+/* Zero-offset stack of every sample of t0_grid along the operator given by
+ * params (device [n_out][n_t][P], as ens_search writes them): the mean over
+ * the traces that take part in that sample's semblance of the amplitude
+ * interpolated at each trace's traveltime, 0 for an empty fold, computed from
+ * the binary32 copy of the traces (sections "Traveltime parameter search",
+ * "Qualitative analysis").  stack_out: device [n_out][n_t].  If S (device
+ * [n_out][n_t], e.g. ens_result.S) and coherence_rms (host) are both given,
+ * *coherence_rms receives sqrt(sum S^2 / (n_out n_t)) in binary64, the RMS of
+ * the coherence panel (section "Quantitative analysis"); the call then waits
+ * for the stream.  Errors as for ens_search's grid. */
+ens_status ens_stack(ens_ctx *ctx, const ens_t0_grid *t0_grid, const float *params, float *stack_out,
+                     const float *S, double *coherence_rms);
+
 /* ---- checks of the device building blocks -------------------------------- */
 
 /* Philox-4x64-10 blocks (Salmon et al., SC'11) for n counters (device

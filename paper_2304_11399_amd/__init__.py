@@ -117,6 +117,7 @@ _SIGS = {
     "ens_quantize": (C.c_int, [_P, _P, C.c_int64, C.c_int32, C.c_int64, C.c_int32, _P, _P]),
     "ens_search": (C.c_int, [_P, C.POINTER(T0Grid), C.POINTER(Bounds), C.POINTER(DeCfg),
                              C.c_uint64, C.POINTER(Result)]),
+    "ens_stack": (C.c_int, [_P, C.POINTER(T0Grid), _P, _P, _P, C.POINTER(C.c_double)]),
     "semblance_eval": (C.c_int, [_P, C.POINTER(Candidates), _P, _P]),
     "semblance_eval64": (C.c_int, [_P, C.POINTER(Candidates), _P]),
     "semblance_backward": (C.c_int, [_P, C.POINTER(Candidates), _P, _P]),
@@ -269,6 +270,27 @@ class Context:
                                          C.c_uint64(int(seed)), C.byref(res)))
         return dict(params=params, S=S, S64=S64, S_pre_polish=S_pre, n_evals=int(res.n_evals),
                     sum_m=int(res.sum_m))
+
+    def stack(self, params, S=None, cmp_out=None, t_begin=0, t_end=None):
+        """Zero-offset stack along each sample's operator (device [n_out, n_t]),
+        and the RMS of the coherence panel S when S is given (else None)."""
+        import torch
+        _require_cuda(params, S)
+        t_end = self.nt if t_end is None else int(t_end)
+        n_out = self.n_cmp if cmp_out is None else len(cmp_out)
+        n_t = t_end - t_begin
+        assert params.dtype == torch.float32 and params.is_contiguous()
+        assert params.numel() == n_out * n_t * self.nparam
+        if S is not None:
+            assert S.dtype == torch.float32 and S.is_contiguous() and S.numel() == n_out * n_t
+        co = None if cmp_out is None else np.ascontiguousarray(cmp_out, dtype=np.int32)
+        grid = _sized(T0Grid, cmp_out=None if co is None else co.ctypes.data, n_cmp_out=n_out,
+                      t_begin=int(t_begin), t_end=t_end)
+        out = torch.empty((n_out, n_t), dtype=torch.float32, device=params.device)
+        rms = C.c_double(0.0)
+        self._check(self._lib.ens_stack(self._h, C.byref(grid), _ptr(params), _ptr(out), _ptr(S),
+                                        None if S is None else C.byref(rms)))
+        return out, (None if S is None else rms.value)
 
     # -------------------------------------------------------------- objective
     def _cands(self, cmp, t, params):

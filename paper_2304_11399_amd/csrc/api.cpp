@@ -786,6 +786,46 @@ ens_status semblance_backward(ens_ctx *ctx, const ens_candidates *cands, const f
     return ENS_OK;
 }
 
+ens_status ens_stack(ens_ctx *ctx, const ens_t0_grid *grid, const float *params, float *stack_out, const float *S,
+                     double *coherence_rms)
+{
+    if (!ctx) return ENS_E_INVALID;
+    if (!ctx->bound) return fail(ctx, ENS_E_STATE, "ens_stack: call ens_bind first");
+    if (!grid || !params || !stack_out) return fail(ctx, ENS_E_INVALID, "ens_stack: null argument");
+    if (grid->struct_size < sizeof(ens_t0_grid)) return fail(ctx, ENS_E_INVALID, "ens_stack: struct_size too small");
+    if ((S == nullptr) != (coherence_rms == nullptr))
+        return fail(ctx, ENS_E_INVALID, "ens_stack: S and coherence_rms go together");
+    const int32_t n_out = grid->cmp_out ? grid->n_cmp_out : ctx->n_cmp;
+    if (n_out < 1) return fail(ctx, ENS_E_INVALID, "ens_stack: no output CMPs");
+    if (grid->cmp_out)
+        for (int32_t o = 0; o < n_out; ++o)
+            if (grid->cmp_out[o] < 0 || grid->cmp_out[o] >= ctx->n_cmp)
+                return fail(ctx, ENS_E_RANGE, "ens_stack: cmp_out[%d] = %d out of range", o, grid->cmp_out[o]);
+    if (grid->t_begin < 0 || grid->t_end > ctx->nt || grid->t_begin >= grid->t_end)
+        return fail(ctx, ENS_E_RANGE, "ens_stack: need 0 <= t_begin < t_end <= nt");
+    const int32_t n_t = grid->t_end - grid->t_begin;
+    hipStream_t st = ctx->stream;
+    std::vector<int32_t> cmp_out(static_cast<size_t>(n_out));
+    for (int32_t o = 0; o < n_out; ++o) cmp_out[o] = grid->cmp_out ? grid->cmp_out[o] : o;
+    HIP_OR_FAIL(ctx, ctx->cmp_out.ensure(cmp_out.size() * sizeof(int32_t)));
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->cmp_out.p, cmp_out.data(), cmp_out.size() * sizeof(int32_t),
+                                    hipMemcpyHostToDevice, st));
+    HIP_OR_FAIL(ctx, ens::launch_stack(ctx->op, view_of(ctx, true), ctx->cmp_out.as<int32_t>(), n_out,
+                                       grid->t_begin, n_t, params, stack_out, st));
+    if (S) {
+        HIP_OR_FAIL(ctx, ctx->flag.ensure(sizeof(double)));
+        double *dev = static_cast<double *>(ctx->flag.p);
+        HIP_OR_FAIL(ctx, ens::launch_rms(S, static_cast<int64_t>(n_out) * n_t, dev, st));
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(coherence_rms, dev, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_OR_FAIL(ctx, hipStreamSynchronize(st));
+    } else {
+        // the host-side cmp_out copy must outlive the asynchronous upload
+        HIP_OR_FAIL(ctx, hipStreamSynchronize(st));
+    }
+    ctx->err.clear();
+    return ENS_OK;
+}
+
 ens_status ens_philox(ens_ctx *ctx, int64_t n, const uint64_t *counters, const uint64_t *key, uint64_t *out)
 {
     if (!ctx) return ENS_E_INVALID;

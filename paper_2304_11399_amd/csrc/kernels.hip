@@ -626,6 +626,69 @@ __global__ __launch_bounds__(256) void k_interp(InterpArgs a)
     }
 }
 
+// Zero-offset stack of every grid sample along its operator: the mean over
+// the participating traces of the amplitude interpolated at the traveltime
+// (0 for an empty fold), from the binary32 copy of the traces (sections
+// "Traveltime parameter search", "Qualitative analysis").  Lane = sample.
+template <int OP>
+__global__ __launch_bounds__(256) void k_stack(StoreView sv, const int32_t *__restrict__ cmp_out, int32_t n_out,
+                                               int32_t t_begin, int32_t n_t, const float *__restrict__ params,
+                                               float *__restrict__ out)
+{
+    const int64_t total = static_cast<int64_t>(n_out) * n_t;
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const bool live = c < total;
+    const int64_t cc = live ? c : total - 1;
+    const int32_t o = static_cast<int32_t>(cc / n_t);
+    const int32_t n0 = t_begin + static_cast<int32_t>(cc - static_cast<int64_t>(o) * n_t);
+    const int32_t j = cmp_out[o];
+    const int32_t ap = sv.ap_tab[n0];
+    float p[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int d = 0; d < OP; ++d) p[d] = params[cc * OP + d];
+    const Cand<float> cand = make_cand<OP, float>(p, n0, j, ap, sv.nt, sv.dt, sv.dx);
+    int32_t c_lo, c_hi;
+    wave_cmp_range(sv, j, ap, live, c_lo, c_hi);
+    const float *store = static_cast<const float *>(sv.store);
+    const ENS_CONST_AS int64_t *cmp_ptr = const_view(sv.cmp_ptr);
+    const ENS_CONST_AS TraceMeta *meta = const_view(sv.meta);
+    float sum = 0.0f;
+    int32_t M = 0;
+    for (int32_t cm = c_lo; cm <= c_hi; ++cm) {
+        const CmpTerm<float> ct = cmp_term(cand, cm, sv.dx);
+        const int32_t i1 = static_cast<int32_t>(cmp_ptr[cm + 1]);
+        for (int32_t i = static_cast<int32_t>(cmp_ptr[cm]); i < i1; ++i) {
+            // a one-sample window: off is the column of the sample before the traveltime
+            const TT<float> tt = traveltime<1>(cand, ct, meta[i].h2);
+            const float *row = store + static_cast<size_t>(i) * sv.ld;
+            const float u0 = row[tt.off], u1 = row[tt.off + 1];
+            sum += fmadd(tt.f, u1, (1.0f - tt.f) * u0);
+            M += tt.ok ? 1 : 0;
+        }
+    }
+    if (live) out[c] = M > 0 ? sum / static_cast<float>(M) : 0.0f;
+}
+
+// Root mean square of a panel in binary64, one workgroup, fixed summation
+// order (section "Quantitative analysis": methods compared by the RMS of
+// their coherence panels).
+__global__ __launch_bounds__(1024) void k_rms(const float *__restrict__ x, int64_t n, double *__restrict__ out)
+{
+    __shared__ double part[1024];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) {
+        const double v = static_cast<double>(x[i]);
+        s = __builtin_fma(v, v, s);
+    }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (static_cast<int>(threadIdx.x) < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = n > 0 ? __builtin_sqrt(part[0] / static_cast<double>(n)) : 0.0;
+}
+
 template <int OP, int DT, int W, int KIND>
 __global__ __launch_bounds__(512) void k_search(SearchArgs a)
 {
@@ -871,6 +934,26 @@ hipError_t launch_search(int op, int dtype, int window, int kind, int dense, con
         ENS_DISPATCH_OP(op, ENS_DISPATCH_DT(dtype, ENS_DISPATCH_W(window,
             hipLaunchKernelGGL((k_search_dense<OP, DT, W, 1>), grid, block, lds, s, a))));
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_stack(int op, const StoreView &sv_f32, const int32_t *cmp_out, int32_t n_out, int32_t t_begin,
+                        int32_t n_t, const float *params, float *out, hipStream_t s)
+{
+    const int64_t total = static_cast<int64_t>(n_out) * n_t;
+    if (total == 0) return hipSuccess;
+    if (op == 1)
+        hipLaunchKernelGGL(k_stack<1>, dim3(blocks_for(total, 256)), dim3(256), 0, s, sv_f32, cmp_out, n_out,
+                           t_begin, n_t, params, out);
+    else
+        hipLaunchKernelGGL(k_stack<3>, dim3(blocks_for(total, 256)), dim3(256), 0, s, sv_f32, cmp_out, n_out,
+                           t_begin, n_t, params, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_rms(const float *x, int64_t n, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_rms, dim3(1), dim3(1024), 0, s, x, n, out);
     return hipGetLastError();
 }
 

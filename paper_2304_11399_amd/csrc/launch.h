@@ -90,6 +90,9 @@ hipError_t launch_eval64_grid(int op, int window, const StoreView &sv_f32, const
                               double *S, hipStream_t s);
 hipError_t launch_backward(int op, int dtype, int window, const StoreView &sv, const CandView &cv,
                            const float *dS, float *g, hipStream_t s);
+hipError_t launch_stack(int op, const StoreView &sv_f32, const int32_t *cmp_out, int32_t n_out, int32_t t_begin,
+                        int32_t n_t, const float *params, float *out, hipStream_t s);
+hipError_t launch_rms(const float *x, int64_t n, double *out, hipStream_t s);
 hipError_t launch_search(int op, int dtype, int window, int kind, int dense, const SearchArgs &a,
                          int32_t n_blocks, hipStream_t s);
 hipError_t launch_polish(int op, int dtype, int window, const PolishArgs &a, hipStream_t s);
