@@ -35,7 +35,7 @@ class _DeCfg(C.Structure):
                 ("np_bf", C.c_int32), ("ng_bf", C.c_int32), ("n_cycle", C.c_int32),
                 ("n_bucket", C.c_int32), ("ens_enabled", C.c_int32), ("inject", C.c_int32),
                 ("F", C.c_float), ("CR", C.c_float), ("objective", C.c_int32),
-                ("n_skip", C.c_int32)]
+                ("n_skip", C.c_int32), ("adapt", C.c_int32)]
 
 
 def build(verbose=False):
@@ -80,6 +80,8 @@ def lib():
         L.or_sref.argtypes = [C.POINTER(_Line), C.POINTER(_Bounds), C.c_int64, P, P, P,
                               C.c_int32, P, P]
         L.or_stack_batch.argtypes = [C.POINTER(_Line), C.c_int64, P, P, P, P, P]
+        L.or_jade_draws.argtypes = [P, C.c_double, C.c_double, C.c_int32, P, P, P]
+        L.or_jade_trial.argtypes = [C.c_int32, C.c_int32, P, P, P, C.c_int32, P, P, P, P, P, P]
         L.or_rms.argtypes = [P, C.c_int64]
         L.or_rms.restype = C.c_double
         _lib = L
@@ -216,7 +218,7 @@ def de_cfg(de, objective=0, inject=1):
     return _DeCfg(int(de["np_lo"]), int(de["np_hi"]), int(de["ng_f"]), int(de["np_bf"]),
                   int(de["ng_bf"]), int(de["n_cycle"]), int(de["n_bucket"]),
                   int(de["ens_enabled"]), int(inject), float(de["F"]), float(de["CR"]),
-                  int(objective), int(de.get("n_skip", 0)))
+                  int(objective), int(de.get("n_skip", 0)), int(de.get("adapt", 0)))
 
 
 def pop_size(de, nt, n0):
@@ -248,6 +250,38 @@ def rms(x):
     """Root mean square of a panel (binary64)."""
     x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1)
     return float(lib().or_rms(_ptr(x), x.size))
+
+
+def jade_draws(words, mu_cr, mu_f, np_):
+    """JADE's per-slot draws for blocks words [n][4]: (k_cr, k_f, a_idx) arrays."""
+    words = np.ascontiguousarray(words, dtype=np.uint64).reshape(-1, 4)
+    n = words.shape[0]
+    k_cr = np.zeros(n, np.int32)
+    k_f = np.zeros(n, np.int32)
+    a_idx = np.zeros(n, np.int32)
+    one_cr, one_f, one_a = C.c_int32(), C.c_int32(), C.c_int32()
+    for i in range(n):
+        lib().or_jade_draws(_ptr(words[i]), float(mu_cr), float(mu_f), int(np_), C.byref(one_cr),
+                            C.byref(one_f), C.byref(one_a))
+        k_cr[i], k_f[i], a_idx[i] = one_cr.value, one_f.value, one_a.value
+    return k_cr, k_f, a_idx
+
+
+def jade_trial(pop, S, archive, words, k_f, k_cr, lo, hi):
+    """One JADE generation's trials (binary32) for population pop [np][P]."""
+    pop = np.ascontiguousarray(pop, dtype=np.float32)
+    np_, P = pop.shape
+    archive = np.ascontiguousarray(archive, dtype=np.float32).reshape(-1, P)
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    words = np.ascontiguousarray(words, dtype=np.uint64).reshape(np_, 4)
+    k_f = np.ascontiguousarray(k_f, dtype=np.int32)
+    k_cr = np.ascontiguousarray(k_cr, dtype=np.int32)
+    lo = np.ascontiguousarray(lo, dtype=np.float32)
+    hi = np.ascontiguousarray(hi, dtype=np.float32)
+    trial = np.zeros_like(pop)
+    lib().or_jade_trial(np_, P, _ptr(pop), _ptr(S), _ptr(archive), archive.shape[0], _ptr(words),
+                        _ptr(k_f), _ptr(k_cr), _ptr(lo), _ptr(hi), _ptr(trial))
+    return trial
 
 
 def quantize(u, dtype):

@@ -53,6 +53,7 @@ typedef struct {
     float F, CR;
     int32_t objective;      /* 0 semblance; 1 sphere mock; 2 needle mock */
     int32_t n_skip;         /* N_skip: time samples interpolated between estimated ones (0..2) */
+    int32_t adapt;          /* 1: JADE control-parameter adaptation and archive (F, CR: initial means) */
 } or_de_cfg;
 
 /* OpenMP threads the oracle's parallel loops use. */
@@ -81,6 +82,21 @@ void or_semblance_grad_batch(const or_line *L, int64_t n, const int32_t *cmp, co
  * pop, trial: [np][P]; S: [np]; words: [np][4] (the four 64-bit outputs). */
 void or_de_trial(int32_t np, int32_t P, const float *pop, const double *S, const uint64_t *words,
                  float F, float CR, const float *lo, const float *hi, float *trial);
+
+/* JADE control parameters of one slot and one generation from the slot's
+ * adaptation block w (Philox counter (sample, stage + 2^32, generation,
+ * slot)): CR and F on the grid k / 2^24 (k_cr in [0, 2^24], k_f in
+ * [1, 2^24]) and the archive position a replaced parent overwrites when the
+ * archive is full. */
+void or_jade_draws(const uint64_t w[4], double mu_cr, double mu_f, int32_t np, int32_t *k_cr,
+                   int32_t *k_f, int32_t *a_idx);
+
+/* One JADE generation's trial vectors: current-to-best/1 with the second
+ * difference vector drawn from population plus archive (archive: [n_arch][P]),
+ * per-slot F = k_f / 2^24 and CR = k_cr / 2^24; words: the slots' DE blocks. */
+void or_jade_trial(int32_t np, int32_t P, const float *pop, const double *S, const float *archive,
+                   int32_t n_arch, const uint64_t *words, const int32_t *k_f, const int32_t *k_cr,
+                   const float *lo, const float *hi, float *trial);
 
 /* Whole search.  cmp_out: [n_out] output CMPs; time indices [t_begin, t_end).
  * params_out: [n_out][n_t][P]; S_out: [n_out][n_t].  Returns evaluations. */

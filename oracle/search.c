@@ -12,10 +12,25 @@
  * every comparison is made (Selection).  After NG generations the best is
  * returned.  Evaluations per domain: NP (1 + NG) (eq. jade_semblance).
  *
- * Fixed-F, fixed-CR reading: the paper takes JADE's parameter adaptation and
- * archive from earlier work without stating them; this oracle uses constant
- * F and CR, binomial crossover with one forced dimension, and midpoint repair
- * of out-of-box mutant coordinates toward the parent.
+ * Control parameters.  The paper runs JADE with archive in every domain and
+ * takes its adaptation from earlier work without stating it (sections
+ * "Selection", "Evolution by neighborhood similarity").  adapt = 0: constant
+ * F and CR.  adapt = 1: JADE (Zhang and Sanderson, 2009) with P = 1:
+ *   - per generation and slot, CR_i ~ N(mu_CR, 0.1) clipped to [0, 1] and
+ *     F_i ~ Cauchy(mu_F, 0.1), 1 where above 1, redrawn where not positive
+ *     (three draws, then mu_F); both are kept on the grid k / 2^24 so that
+ *     their sums below are exact integers;
+ *   - the second difference vector's minuend x_r2 comes from the population
+ *     joined with the archive A of replaced parents (|A| <= NP);
+ *   - every replaced parent enters A (appended while |A| < NP, else
+ *     overwriting a uniformly drawn position), in slot order;
+ *   - after the generation, when some trial replaced its parent,
+ *     mu_CR <- 0.9 mu_CR + 0.1 mean(CR of those slots) and
+ *     mu_F <- 0.9 mu_F + 0.1 sum F^2 / sum F over them (Lehmer mean);
+ *   - each domain (sample and stage) starts from mu_CR = CR, mu_F = F and an
+ *     empty archive.
+ * Binomial crossover has one forced dimension, and out-of-box mutant
+ * coordinates are repaired to the midpoint between bound and parent.
  *
  * Random numbers: one Philox-4x64-10 block per (sample, stage, generation,
  * slot), key (seed, 0).  Generation 0 words 0..2 give the initial coordinates
@@ -23,7 +38,13 @@
  * halves draw r1 in [0,NP-1) and r2 in [0,NP-2) by multiply-shift, skipping
  * the excluded indices in ascending order; word 1 high half draws the forced
  * dimension; word 1 low, word 2 high, word 2 low are the crossover draws of
- * dimensions 0, 1, 2, compared against ceil(CR 2^32).
+ * dimensions 0, 1, 2, compared against ceil(CR 2^32).  With the archive, r2
+ * is drawn in [0, NP + |A| - 2) the same way (indices from NP on name
+ * archive entries).  JADE's draws come from a second block per (sample,
+ * generation, slot), stage word + 2^32: words 0 and 1 (top 53 bits) give the
+ * Box-Muller normal for CR, the halves of word 2 and the high half of word 3
+ * the Cauchy draws for F (inverse CDF), the low half of word 3 the archive
+ * position.
  *
  * ENS (sections "Information propagation" and "Evolution by neighborhood
  * similarity"), first with N_skip = 0: stage 0 sweeps each interactive domain (bucket of
@@ -152,6 +173,86 @@ void or_de_trial(int32_t np, int32_t P, const float *pop, const double *S, const
     }
 }
 
+#define JADE_GRID 16777216.0 /* 2^24 */
+#define PI_D 3.14159265358979323846
+
+void or_jade_draws(const uint64_t w[4], double mu_cr, double mu_f, int32_t np, int32_t *k_cr,
+                   int32_t *k_f, int32_t *a_idx)
+{
+    /* CR: Box-Muller normal from two 53-bit uniforms, u1 in (0, 1] */
+    const double u1 = ((double)(w[0] >> 11) + 1.0) * 0x1p-53;
+    const double u2 = (double)(w[1] >> 11) * 0x1p-53;
+    const double z = sqrt(-2.0 * log(u1)) * cos(2.0 * PI_D * u2);
+    double cr = mu_cr + 0.1 * z;
+    if (cr < 0.0)
+        cr = 0.0;
+    if (cr > 1.0)
+        cr = 1.0;
+    *k_cr = (int32_t)nearbyint(cr * JADE_GRID);
+    /* F: Cauchy by the inverse CDF from 32-bit uniforms in (0, 1) */
+    const uint64_t h[3] = {w[2] >> 32, w[2] & 0xffffffffULL, w[3] >> 32};
+    int32_t kf = 0;
+    for (int a = 0; a < 3 && kf == 0; ++a) {
+        const double u = ((double)h[a] + 0.5) * 0x1p-32;
+        double f = mu_f + 0.1 * tan(PI_D * (u - 0.5));
+        if (f > 1.0)
+            f = 1.0;
+        if (f > 0.0)
+            kf = (int32_t)nearbyint(f * JADE_GRID);
+    }
+    if (kf == 0) {
+        kf = (int32_t)nearbyint(mu_f * JADE_GRID);
+        if (kf < 1)
+            kf = 1;
+    }
+    *k_f = kf;
+    *a_idx = (int32_t)(((w[3] & 0xffffffffULL) * (uint64_t)np) >> 32);
+}
+
+void or_jade_trial(int32_t np, int32_t P, const float *pop, const double *S, const float *archive,
+                   int32_t n_arch, const uint64_t *words, const int32_t *k_f, const int32_t *k_cr,
+                   const float *lo, const float *hi, float *trial)
+{
+    int32_t b = 0;
+    for (int32_t i = 1; i < np; ++i)
+        if (S[i] > S[b])
+            b = i;
+    const int32_t total = np + n_arch;
+    for (int32_t i = 0; i < np; ++i) {
+        const uint64_t *w = words + 4 * i;
+        uint32_t r1 = (uint32_t)(((w[0] >> 32) * (uint64_t)(np - 1)) >> 32);
+        if (r1 >= (uint32_t)i)
+            r1 += 1;
+        uint32_t r2 = (uint32_t)(((w[0] & 0xffffffffULL) * (uint64_t)(total - 2)) >> 32);
+        uint32_t ex_lo = (uint32_t)i < r1 ? (uint32_t)i : r1;
+        uint32_t ex_hi = (uint32_t)i < r1 ? r1 : (uint32_t)i;
+        if (r2 >= ex_lo)
+            r2 += 1;
+        if (r2 >= ex_hi)
+            r2 += 1;
+        const float *x2 = r2 < (uint32_t)np ? pop + r2 * P : archive + (r2 - (uint32_t)np) * P;
+        uint32_t jr = (uint32_t)(((w[1] >> 32) * (uint64_t)P) >> 32);
+        uint64_t cr[3] = {w[1] & 0xffffffffULL, w[2] >> 32, w[2] & 0xffffffffULL};
+        const uint64_t thr = (uint64_t)k_cr[i] << 8; /* CR 2^32, exact on the grid */
+        const float F = (float)k_f[i] * 0x1p-24f;
+        for (int d = 0; d < P; ++d) {
+            float xi = pop[i * P + d];
+            float t1 = pop[b * P + d] - xi;
+            float t2 = pop[r1 * P + d] - x2[d];
+            float m1 = F * t1;
+            float m2 = F * t2;
+            float v = xi + m1;
+            v = v + m2;
+            if (v < lo[d])
+                v = (lo[d] + xi) * 0.5f;
+            else if (v > hi[d])
+                v = (hi[d] + xi) * 0.5f;
+            int take = (cr[d] < thr) || ((uint32_t)d == jr);
+            trial[i * P + d] = take ? v : xi;
+        }
+    }
+}
+
 /* ---------------------------------------------------------------------------
  * objective */
 
@@ -195,19 +296,47 @@ static int64_t evolve(const objective_ctx *o, uint64_t seed, uint64_t sample, ui
     double St[MAXNP];
     uint64_t words[MAXNP * 4];
     int64_t evals = 0;
+    const int adapt = o->cfg->adapt;
+    double mu_cr = (double)o->cfg->CR, mu_f = (double)o->cfg->F;
+    float archive[MAXNP * 3];
+    int32_t n_arch = 0, k_cr[MAXNP], k_f[MAXNP], a_idx[MAXNP];
     for (int g = 1; g <= ng; ++g) {
         for (int i = 0; i < np; ++i)
             rng_words(seed, sample, stage, (uint64_t)g, (uint64_t)i, words + 4 * i);
-        or_de_trial(np, P, pop, S, words, o->cfg->F, o->cfg->CR, lo, hi, trial);
+        if (adapt) {
+            for (int i = 0; i < np; ++i) {
+                uint64_t jw[4];
+                rng_words(seed, sample, stage + (1ULL << 32), (uint64_t)g, (uint64_t)i, jw);
+                or_jade_draws(jw, mu_cr, mu_f, np, &k_cr[i], &k_f[i], &a_idx[i]);
+            }
+            or_jade_trial(np, P, pop, S, archive, n_arch, words, k_f, k_cr, lo, hi, trial);
+        } else {
+            or_de_trial(np, P, pop, S, words, o->cfg->F, o->cfg->CR, lo, hi, trial);
+        }
         for (int i = 0; i < np; ++i) {
             St[i] = objective(o, j, n0, trial + i * P, lo, hi);
             ++evals;
         }
+        int64_t n_succ = 0, sum_cr = 0, sum_f = 0, sum_f2 = 0;
         for (int i = 0; i < np; ++i) {
             if (St[i] >= S[i]) {
+                if (adapt) {
+                    float *dst = n_arch < np ? archive + (n_arch++) * P : archive + a_idx[i] * P;
+                    memcpy(dst, pop + i * P, sizeof(float) * (size_t)P);
+                    n_succ += 1;
+                    sum_cr += k_cr[i];
+                    sum_f += k_f[i];
+                    sum_f2 += (int64_t)k_f[i] * k_f[i];
+                }
                 memcpy(pop + i * P, trial + i * P, sizeof(float) * (size_t)P);
                 S[i] = St[i];
             }
+        }
+        if (adapt && n_succ > 0) {
+            const double mean_cr = (double)sum_cr / ((double)n_succ * JADE_GRID);
+            const double lehmer_f = (double)sum_f2 / ((double)sum_f * JADE_GRID);
+            mu_cr = 0.9 * mu_cr + 0.1 * mean_cr;
+            mu_f = 0.9 * mu_f + 0.1 * lehmer_f;
         }
     }
     return evals;
