@@ -107,8 +107,9 @@ def cpu_baseline(g, wl, de, bounds):
 
 
 def compare_equal_accuracy(ctx, bounds, wl, store, g, run_main):
-    """ENS (without and with the paper's N_skip = 2 time skipping) against the
-    per-sample search the paper compares with, each over a
+    """ENS (without and with the paper's N_skip = 2 time skipping, with fixed F
+    and CR and with JADE's adaptation) against the per-sample search the paper
+    compares with, each over a
     few budgets: the fastest budget whose mean gap to the reference maxima is
     <= 1e-3 is each method's throughput at that accuracy."""
     import torch
@@ -121,6 +122,12 @@ def compare_equal_accuracy(ctx, bounds, wl, store, g, run_main):
                 ("ens_skip2", dict(de0, n_skip=2)),
                 ("ens_skip2", dict(de0, np_lo=16, np_hi=16, ng_f=20, n_skip=2)),
                 ("ens_skip2", dict(de0, np_lo=16, np_hi=16, ng_f=10, n_skip=2)),
+                ("ens_jade", dict(de0, adapt=1, CR=0.5)),
+                ("ens_jade", dict(de0, np_lo=16, np_hi=16, ng_f=20, adapt=1, CR=0.5)),
+                ("ens_jade", dict(de0, np_lo=16, np_hi=16, ng_f=10, adapt=1, CR=0.5)),
+                ("plain_jade", dict(de0, ens_enabled=0, np_lo=16, np_hi=16, ng_f=20, adapt=1, CR=0.5)),
+                ("plain_jade", dict(de0, ens_enabled=0, ng_f=40, adapt=1, CR=0.5)),
+                ("plain_jade", dict(de0, ens_enabled=0, adapt=1, CR=0.5)),
                 ("plain", dict(de0, ens_enabled=0, np_lo=16, np_hi=16, ng_f=20)),
                 ("plain", dict(de0, ens_enabled=0, ng_f=40)),
                 ("plain", dict(de0, ens_enabled=0)),
@@ -136,7 +143,7 @@ def compare_equal_accuracy(ctx, bounds, wl, store, g, run_main):
         sec = time.perf_counter() - t0
         gap = gap_stats(wl["name"], out["S64"].cpu().numpy(), g.nt, g)
         rows.append({"method": kind, "np": de["np_lo"], "ng": de["ng_f"],
-                     "n_skip": de.get("n_skip", 0),
+                     "n_skip": de.get("n_skip", 0), "adapt": de.get("adapt", 0),
                      "ms": round(1e3 * sec, 2), "zo_samples_per_s": round(g.n_cmp * g.nt / sec, 1),
                      "evals": out["n_evals"], "gap_mean": gap["mean"] if gap else None,
                      "frac_le_1e-3": gap["frac_le_1e-3"] if gap else None})
@@ -152,7 +159,8 @@ def compare_equal_accuracy(ctx, bounds, wl, store, g, run_main):
         return None
     return {"store": store, "runs": rows, "best_at_gap_le_1e-3": best,
             "ens_over_plain_zo_samples_per_s": ratio("ens", "plain"),
-            "ens_skip2_over_plain_zo_samples_per_s": ratio("ens_skip2", "plain")}
+            "ens_skip2_over_plain_zo_samples_per_s": ratio("ens_skip2", "plain"),
+            "ens_jade_over_plain_jade_zo_samples_per_s": ratio("ens_jade", "plain_jade")}
 
 
 def gap_stats(name, S64, nt, g):

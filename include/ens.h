@@ -136,7 +136,15 @@ typedef struct {
  * higher (sections "The performance-quality trade-off by an interpolation
  * process" and "Evolution by neighborhood similarity", eq. for
  * the ENS evaluation count).  F, CR: fixed mutation factor
- * and crossover rate.  polish_steps > 0: that many Adam steps of learning
+ * and crossover rate.  adapt = 1: JADE with archive in every domain (the
+ * paper's per-domain engine, sections "Selection" and "Evolution by
+ * neighborhood similarity"; its rules are JADE's published ones): per slot
+ * and generation CR ~ N(mu_CR, 0.1) clipped to [0, 1] and F ~ Cauchy(mu_F,
+ * 0.1), cut to 1, redrawn where not positive, both on the grid k / 2^24;
+ * the second difference vector's minuend drawn from population plus
+ * archive of replaced parents (at most NP); after each generation the means
+ * move 10% toward the arithmetic mean of the successful CR and the Lehmer
+ * mean of the successful F; F and CR give the initial means (F in (0, 1]).  polish_steps > 0: that many Adam steps of learning
  * rate polish_lr on box-normalised coordinates per winner, keeping the best
  * point.  rescore_fp64: also write the binary64 semblance of each winner,
  * computed from the binary32 copy of the traces. */
@@ -154,6 +162,7 @@ typedef struct {
     int32_t polish_steps;
     float polish_lr;
     int32_t rescore_fp64;
+    int32_t adapt;
 } ens_de_cfg;
 
 /* Search outputs (device, [n_cmp_out][n_t][P] and [n_cmp_out][n_t]); S64 and
@@ -282,6 +291,14 @@ ens_status ens_stack(ens_ctx *ctx, const ens_t0_grid *t0_grid, const float *para
  * [n][4] uint64) under key (device [2]): out device [n][4]. */
 ens_status ens_philox(ens_ctx *ctx, int64_t n, const uint64_t *counters, const uint64_t *key,
                       uint64_t *out);
+
+/* JADE's per-slot draws for n adaptation blocks (device words [n][4], the
+ * Philox outputs for counter (sample, stage + 2^32, generation, slot)) at
+ * means mu_cr, mu_f: k_cr, k_f, a_idx device [n] (CR = k_cr / 2^24,
+ * F = k_f / 2^24, the archive position for a full archive of np entries).
+ * The search kernels use the same device routine. */
+ens_status ens_jade_draws(ens_ctx *ctx, int64_t n, const uint64_t *words, double mu_cr, double mu_f,
+                          int32_t np, int32_t *k_cr, int32_t *k_f, int32_t *a_idx);
 
 /* One generation's trial vectors of the evolution for n_pop independent
  * populations of size np (device pop [n_pop*np][P], S [n_pop*np], words

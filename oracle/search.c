@@ -175,6 +175,64 @@ void or_de_trial(int32_t np, int32_t P, const float *pop, const double *S, const
 
 #define JADE_GRID 16777216.0 /* 2^24 */
 #define PI_D 3.14159265358979323846
+#define LN2_D 0.693147180559945309417
+
+/* The variates use their own binary64 series (no library transcendental),
+ * each operation written out, so that any IEEE binary64 implementation of
+ * + - * / and sqrt produces the same bits:
+ *   ln u = e ln 2 + 2 atanh((m-1)/(m+1)), u = m 2^e, m in [sqrt(1/2), sqrt(2)),
+ *          atanh by its Taylor series to the s^23 term (|s| <= 0.172);
+ *   sin a, cos a for a in [0, pi/2] by their Taylor series to a^25, a^24. */
+static double jade_ln(double u)
+{
+    int e;
+    double m = frexp(u, &e);
+    if (m < 0.70710678118654752440) {
+        m = m * 2.0;
+        e = e - 1;
+    }
+    const double s = (m - 1.0) / (m + 1.0);
+    const double s2 = s * s;
+    double p = 1.0 / 23.0;
+    for (int k = 21; k >= 1; k -= 2)
+        p = p * s2 + 1.0 / (double)k;
+    return (double)e * LN2_D + 2.0 * s * p;
+}
+
+static void jade_sincos(double a, double *sn, double *cs)
+{
+    const double a2 = a * a;
+    double ps = 1.0, pc = 1.0;
+    /* Horner from the highest term: sin a = a (1 - a^2/(2 3) (1 - a^2/(4 5) (...))) */
+    for (int k = 24; k >= 2; k -= 2) {
+        ps = 1.0 - ps * a2 / (double)((k) * (k + 1));
+        pc = 1.0 - pc * a2 / (double)((k - 1) * (k));
+    }
+    *sn = a * ps;
+    *cs = pc;
+}
+
+/* cos(2 pi t), t in [0, 1): quarter turn q and the angle within it */
+static double jade_cos_turns(double t)
+{
+    const double v = 4.0 * t;
+    const double q = floor(v);
+    const double a = (v - q) * (PI_D / 2.0);
+    double sn, cs;
+    jade_sincos(a, &sn, &cs);
+    const int iq = (int)q;
+    return iq == 0 ? cs : (iq == 1 ? -sn : (iq == 2 ? -cs : sn));
+}
+
+/* tan(pi x), x in (-1/2, 1/2) */
+static double jade_tan_half_turn(double x)
+{
+    const double y = x < 0.0 ? -x : x;
+    double sn, cs;
+    jade_sincos(y * PI_D, &sn, &cs);
+    const double t = sn / cs;
+    return x < 0.0 ? -t : t;
+}
 
 void or_jade_draws(const uint64_t w[4], double mu_cr, double mu_f, int32_t np, int32_t *k_cr,
                    int32_t *k_f, int32_t *a_idx)
@@ -182,7 +240,7 @@ void or_jade_draws(const uint64_t w[4], double mu_cr, double mu_f, int32_t np, i
     /* CR: Box-Muller normal from two 53-bit uniforms, u1 in (0, 1] */
     const double u1 = ((double)(w[0] >> 11) + 1.0) * 0x1p-53;
     const double u2 = (double)(w[1] >> 11) * 0x1p-53;
-    const double z = sqrt(-2.0 * log(u1)) * cos(2.0 * PI_D * u2);
+    const double z = sqrt(-2.0 * jade_ln(u1)) * jade_cos_turns(u2);
     double cr = mu_cr + 0.1 * z;
     if (cr < 0.0)
         cr = 0.0;
@@ -194,7 +252,7 @@ void or_jade_draws(const uint64_t w[4], double mu_cr, double mu_f, int32_t np, i
     int32_t kf = 0;
     for (int a = 0; a < 3 && kf == 0; ++a) {
         const double u = ((double)h[a] + 0.5) * 0x1p-32;
-        double f = mu_f + 0.1 * tan(PI_D * (u - 0.5));
+        double f = mu_f + 0.1 * jade_tan_half_turn(u - 0.5);
         if (f > 1.0)
             f = 1.0;
         if (f > 0.0)

@@ -64,7 +64,7 @@ class DeCfg(C.Structure):
                 ("n_cycle", C.c_int32), ("n_skip", C.c_int32), ("n_bucket", C.c_int32),
                 ("ens_enabled", C.c_int32), ("inject", C.c_int32), ("F", C.c_float),
                 ("CR", C.c_float), ("polish_steps", C.c_int32), ("polish_lr", C.c_float),
-                ("rescore_fp64", C.c_int32)]
+                ("rescore_fp64", C.c_int32), ("adapt", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -118,6 +118,7 @@ _SIGS = {
     "ens_search": (C.c_int, [_P, C.POINTER(T0Grid), C.POINTER(Bounds), C.POINTER(DeCfg),
                              C.c_uint64, C.POINTER(Result)]),
     "ens_stack": (C.c_int, [_P, C.POINTER(T0Grid), _P, _P, _P, C.POINTER(C.c_double)]),
+    "ens_jade_draws": (C.c_int, [_P, C.c_int64, _P, C.c_double, C.c_double, C.c_int32, _P, _P, _P]),
     "semblance_eval": (C.c_int, [_P, C.POINTER(Candidates), _P, _P]),
     "semblance_eval64": (C.c_int, [_P, C.POINTER(Candidates), _P]),
     "semblance_backward": (C.c_int, [_P, C.POINTER(Candidates), _P, _P]),
@@ -335,6 +336,17 @@ class Context:
                                          _ptr(out)))
         return out
 
+    def jade_draws(self, words, mu_cr, mu_f, np_):
+        """JADE's draws for adaptation blocks words [n, 4] (uint64 as int64):
+        device int32 tensors k_cr, k_f, a_idx."""
+        import torch
+        _require_cuda(words)
+        n = words.shape[0]
+        outs = [torch.empty(n, dtype=torch.int32, device=words.device) for _ in range(3)]
+        self._check(self._lib.ens_jade_draws(self._h, n, _ptr(words), float(mu_cr), float(mu_f),
+                                             int(np_), *[_ptr(o) for o in outs]))
+        return tuple(outs)
+
     def de_trial(self, pop, S, words, F, CR, lo, hi):
         """pop [n_pop, np, P], S [n_pop, np], words [n_pop, np, 4], lo/hi [n_pop, P]."""
         import torch
@@ -353,7 +365,8 @@ def de_cfg(de, rescore_fp64=True):
                   n_bucket=int(de.get("n_bucket", 1)), ens_enabled=int(de.get("ens_enabled", 0)),
                   inject=int(de.get("inject", 1)), F=float(de["F"]), CR=float(de["CR"]),
                   polish_steps=int(de.get("polish_steps", 0)),
-                  polish_lr=float(de.get("polish_lr", 0.01)), rescore_fp64=int(bool(rescore_fp64)))
+                  polish_lr=float(de.get("polish_lr", 0.01)), rescore_fp64=int(bool(rescore_fp64)),
+                  adapt=int(de.get("adapt", 0)))
 
 
 def ens_search(traces, geometry, t0_grid, bounds, de_cfg_, seed, *, op, window, ap_lo=0,

@@ -348,6 +348,9 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
     }
     if (!finite(de->F) || !finite(de->CR) || de->CR < 0.f || de->CR > 1.f)
         return fail(ctx, ENS_E_RANGE, "ens_search: F must be finite and CR in [0, 1]");
+    if (de->adapt != 0 && de->adapt != 1) return fail(ctx, ENS_E_RANGE, "ens_search: adapt must be 0 or 1");
+    if (de->adapt && !(de->F > 0.f && de->F <= 1.f))
+        return fail(ctx, ENS_E_RANGE, "ens_search: with adapt, F (the initial mean) must lie in (0, 1]");
     if (de->polish_steps < 0 || (de->polish_steps > 0 && !(de->polish_lr > 0.f)))
         return fail(ctx, ENS_E_RANGE, "ens_search: polish needs steps >= 0 and lr > 0");
 
@@ -446,6 +449,8 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
     a.inject = de->inject;
     a.seed = seed;
     a.F = de->F;
+    a.CR = de->CR;
+    a.adapt = de->adapt;
     a.cr_thr = static_cast<uint64_t>(std::ceil(static_cast<double>(de->CR) * 4294967296.0));
     a.counters = ctx->counters.as<unsigned long long>();
 
@@ -563,7 +568,7 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
             std::vector<ens_ctx::Shape> cands;
             for (int ns : nsl_opts)
                 for (int od = 1; od <= 2; ++od)
-                    for (int dn = 0; dn <= 1; ++dn)
+                    for (int dn = 0; dn <= (de->adapt ? 0 : 1); ++dn)  // JADE: one register budget
                         if ((nsl == 0 || ns == nsl) && (order == 0 || od == order) && (dense < 0 || dn == dense))
                             cands.push_back({ns, od, dn});
             ens::SearchArgs ta = first->a;
@@ -846,6 +851,19 @@ ens_status ens_de_trial(ens_ctx *ctx, int32_t n_pop, int32_t np, int32_t P, cons
     if (!finite(F) || !(CR >= 0.f && CR <= 1.f)) return fail(ctx, ENS_E_RANGE, "ens_de_trial: bad F or CR");
     const uint64_t thr = static_cast<uint64_t>(std::ceil(static_cast<double>(CR) * 4294967296.0));
     HIP_OR_FAIL(ctx, ens::launch_de_trial(n_pop, np, P, pop, S, words, F, thr, lo, hi, trial, ctx->stream));
+    ctx->err.clear();
+    return ENS_OK;
+}
+
+ens_status ens_jade_draws(ens_ctx *ctx, int64_t n, const uint64_t *words, double mu_cr, double mu_f, int32_t np,
+                          int32_t *k_cr, int32_t *k_f, int32_t *a_idx)
+{
+    if (!ctx) return ENS_E_INVALID;
+    if (n < 0 || (n > 0 && (!words || !k_cr || !k_f || !a_idx)))
+        return fail(ctx, ENS_E_INVALID, "ens_jade_draws: bad argument");
+    if (np < 4 || np > ENS_MAX_POP) return fail(ctx, ENS_E_RANGE, "ens_jade_draws: np must lie in [4, 64]");
+    if (!finite(mu_cr) || !finite(mu_f)) return fail(ctx, ENS_E_RANGE, "ens_jade_draws: means must be finite");
+    HIP_OR_FAIL(ctx, ens::launch_jade_draws(n, words, mu_cr, mu_f, np, k_cr, k_f, a_idx, ctx->stream));
     ctx->err.clear();
     return ENS_OK;
 }

@@ -312,14 +312,16 @@ struct TrialDraw {
     bool take[3];
 };
 
-// Indices and crossover decisions of one slot from its generator block.
+// Indices and crossover decisions of one slot from its generator block.  r2
+// ranges over a pool of np members plus any archive entries (indices from
+// np on), excluding the slot itself and r1.
 __device__ __forceinline__ TrialDraw trial_draw(const uint64_t w[4], int32_t i, int32_t np, int32_t P,
-                                                uint64_t cr_thr)
+                                                uint64_t cr_thr, int32_t pool)
 {
     TrialDraw d;
     uint32_t r1 = static_cast<uint32_t>(((w[0] >> 32) * static_cast<uint64_t>(np - 1)) >> 32);
     if (r1 >= static_cast<uint32_t>(i)) r1 += 1;
-    uint32_t r2 = static_cast<uint32_t>(((w[0] & 0xffffffffULL) * static_cast<uint64_t>(np - 2)) >> 32);
+    uint32_t r2 = static_cast<uint32_t>(((w[0] & 0xffffffffULL) * static_cast<uint64_t>(pool - 2)) >> 32);
     const uint32_t ui = static_cast<uint32_t>(i);
     const uint32_t ex_lo = ui < r1 ? ui : r1, ex_hi = ui < r1 ? r1 : ui;
     if (r2 >= ex_lo) r2 += 1;
@@ -348,6 +350,89 @@ __device__ __forceinline__ float mutant(float xi, float xb, float xr1, float xr2
     else if (v > hi)
         v = (hi + xi) * 0.5f;
     return v;
+}
+
+// JADE control parameters of one slot from its adaptation block (the same
+// definition as the oracle's): CR ~ N(mu_CR, 0.1) clipped to [0, 1] by
+// Box-Muller, F ~ Cauchy(mu_F, 0.1) by the inverse CDF, 1 where above 1,
+// redrawn where not positive (three draws, then mu_F); both on the grid
+// k / 2^24.  a_idx: archive position a replaced parent overwrites when the
+// archive is full.  Binary64 throughout.  The logarithm, sine and cosine are
+// series on reduced arguments written out operation by operation (ln u =
+// e ln 2 + 2 atanh((m-1)/(m+1)) with m in [sqrt(1/2), sqrt(2)) and atanh to
+// the s^23 term; sin and cos on [0, pi/2] by Taylor series to a^25, a^24):
+// no library routine, so the bits do not depend on a math library, and few
+// registers.
+constexpr double JADE_GRID = 16777216.0;
+constexpr double JADE_PI = 3.14159265358979323846;
+
+__device__ __forceinline__ double jade_ln(double u)
+{
+    int e;
+    double m = frexp(u, &e);
+    if (m < 0.70710678118654752440) {
+        m = m * 2.0;
+        e = e - 1;
+    }
+    const double s = (m - 1.0) / (m + 1.0);
+    const double s2 = s * s;
+    double p = 1.0 / 23.0;
+#pragma unroll
+    for (int k = 21; k >= 1; k -= 2) p = p * s2 + 1.0 / static_cast<double>(k);
+    return static_cast<double>(e) * 0.693147180559945309417 + 2.0 * s * p;
+}
+
+__device__ __forceinline__ void jade_sincos(double a, double &sn, double &cs)
+{
+    const double a2 = a * a;
+    double ps = 1.0, pc = 1.0;
+#pragma unroll
+    for (int k = 24; k >= 2; k -= 2) {
+        ps = 1.0 - ps * a2 / static_cast<double>(k * (k + 1));
+        pc = 1.0 - pc * a2 / static_cast<double>((k - 1) * k);
+    }
+    sn = a * ps;
+    cs = pc;
+}
+
+__device__ __forceinline__ void jade_draws(const uint64_t w[4], double mu_cr, double mu_f, int32_t np,
+                                           int32_t &k_cr, int32_t &k_f, int32_t &a_idx)
+{
+    const double u1 = (static_cast<double>(w[0] >> 11) + 1.0) * 0x1p-53;
+    const double u2 = static_cast<double>(w[1] >> 11) * 0x1p-53;
+    // cos(2 pi u2) from the quarter turn and the angle within it
+    const double v = 4.0 * u2;
+    const double q = floor(v);
+    double sn, cs;
+    jade_sincos((v - q) * (JADE_PI / 2.0), sn, cs);
+    const int iq = static_cast<int>(q);
+    const double c2 = iq == 0 ? cs : (iq == 1 ? -sn : (iq == 2 ? -cs : sn));
+    const double z = sqrt(-2.0 * jade_ln(u1)) * c2;
+    double cr = mu_cr + 0.1 * z;
+    cr = cr < 0.0 ? 0.0 : cr;
+    cr = cr > 1.0 ? 1.0 : cr;
+    k_cr = static_cast<int32_t>(rint(cr * JADE_GRID));
+    const uint64_t h[3] = {w[2] >> 32, w[2] & 0xffffffffULL, w[3] >> 32};
+    int32_t kf = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (kf == 0) {
+            const double u = (static_cast<double>(h[a]) + 0.5) * 0x1p-32;
+            const double x = u - 0.5;  // tan(pi x) = sign(x) sin(pi |x|) / cos(pi |x|)
+            double sx, cx;
+            jade_sincos((x < 0.0 ? -x : x) * JADE_PI, sx, cx);
+            const double tx = sx / cx;
+            double f = mu_f + 0.1 * (x < 0.0 ? -tx : tx);
+            f = f > 1.0 ? 1.0 : f;
+            if (f > 0.0) kf = static_cast<int32_t>(rint(f * JADE_GRID));
+        }
+    }
+    if (kf == 0) {
+        kf = static_cast<int32_t>(rint(mu_f * JADE_GRID));
+        kf = kf < 1 ? 1 : kf;
+    }
+    k_f = kf;
+    a_idx = static_cast<int32_t>(((w[3] & 0xffffffffULL) * static_cast<uint64_t>(np)) >> 32);
 }
 
 __device__ __forceinline__ float init_coord(uint64_t w, float lo, float hi)

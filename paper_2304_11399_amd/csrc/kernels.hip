@@ -320,20 +320,71 @@ __device__ __forceinline__ int32_t group_argmax(float S, int32_t base, int32_t n
 // Trial vector of this lane's slot: current-to-best/1 mutant from the slot,
 // the best and two other random members, binomial crossover (section
 // "Mutation and crossover").  Every lane of the wave must call it.
-template <int P>
+// With an archive (JADE), lane base + a holds archive entry a in `arch`
+// and r2 ranges over the np members and the n_arch entries.
+template <int P, bool ARCHIVE = false>
 __device__ __forceinline__ void make_trial(const float *x, float S, int32_t base, int32_t np,
                                           int32_t slot, const uint64_t w[4], float F, uint64_t cr_thr,
-                                          const float *lo, const float *hi, float *u)
+                                          const float *lo, const float *hi, float *u,
+                                          const float *arch = nullptr, int32_t n_arch = 0)
 {
     const int32_t b = group_argmax(S, base, np);
-    const TrialDraw dr = trial_draw(w, slot, np, P, cr_thr);
+    const TrialDraw dr = trial_draw(w, slot, np, P, cr_thr, ARCHIVE ? np + n_arch : np);
+    const bool from_arch = ARCHIVE && dr.r2 >= static_cast<uint32_t>(np);
+    const int32_t r2_lane = base + static_cast<int32_t>(from_arch ? dr.r2 - np : dr.r2);
 #pragma unroll
     for (int d = 0; d < P; ++d) {
         const float xb = __shfl(x[d], base + b, WAVE);
         const float xr1 = __shfl(x[d], base + static_cast<int32_t>(dr.r1), WAVE);
-        const float xr2 = __shfl(x[d], base + static_cast<int32_t>(dr.r2), WAVE);
+        float xr2 = __shfl(x[d], r2_lane, WAVE);
+        if constexpr (ARCHIVE) {
+            const float ar2 = __shfl(arch[d], r2_lane, WAVE);
+            xr2 = from_arch ? ar2 : xr2;
+        }
         const float v = mutant(x[d], xb, xr1, xr2, F, lo[d], hi[d]);
         u[d] = dr.take[d] ? v : x[d];
+    }
+}
+
+// JADE bookkeeping after a generation's evaluation, in slot order within
+// each population: every slot whose trial replaces its parent (ok) puts the
+// parent into the archive (appended while it holds fewer than np entries,
+// else at that slot's drawn position) and adds its F and CR to the
+// population's sums; then the means move toward the successful values.
+// Every lane of the wave must call it; populations are lane groups.
+template <int P>
+__device__ __forceinline__ void jade_update(bool ok, const float *x, int32_t k_cr, int32_t k_f, int32_t a_idx,
+                                           int32_t grp, int32_t np, int32_t slot, float *arch, int32_t &n_arch,
+                                           double &mu_cr, double &mu_f)
+{
+    uint64_t pending = __ballot(ok);
+    int64_t s_cr = 0, s_f = 0, s_f2 = 0;
+    int32_t n_s = 0;
+    while (pending) {
+        const int32_t L = __builtin_ctzll(pending);
+        pending &= pending - 1;
+        float xs[3];
+#pragma unroll
+        for (int d = 0; d < P; ++d) xs[d] = __shfl(x[d], L, WAVE);
+        const int32_t kc = __shfl(k_cr, L, WAVE), kf = __shfl(k_f, L, WAVE), ai = __shfl(a_idx, L, WAVE);
+        if (L / np == grp) {
+            const int32_t pos = n_arch < np ? n_arch : ai;
+            if (slot == pos) {
+#pragma unroll
+                for (int d = 0; d < P; ++d) arch[d] = xs[d];
+            }
+            n_arch = n_arch < np ? n_arch + 1 : np;
+            n_s += 1;
+            s_cr += kc;
+            s_f += kf;
+            s_f2 += static_cast<int64_t>(kf) * kf;
+        }
+    }
+    if (n_s > 0) {
+        const double mean_cr = static_cast<double>(s_cr) / (static_cast<double>(n_s) * JADE_GRID);
+        const double lehmer_f = static_cast<double>(s_f2) / (static_cast<double>(s_f) * JADE_GRID);
+        mu_cr = 0.9 * mu_cr + 0.1 * mean_cr;
+        mu_f = 0.9 * mu_f + 0.1 * lehmer_f;
     }
 }
 
@@ -417,7 +468,7 @@ __device__ __forceinline__ void pace_by_progress(const unsigned long long *steps
 // exploitation stages.  KIND selects the counters and names the kernel.
 // k_search_dense is the same code held to 64 VGPRs (8 waves per SIMD), for
 // launches whose wave count fits the chip in one round at that occupancy.
-template <int OP, int DT, int W, int KIND>
+template <int OP, int DT, int W, int KIND, bool ADAPT>
 __device__ __forceinline__ void search_body(const SearchArgs &a)
 {
     extern __shared__ float lds[];
@@ -511,18 +562,35 @@ __device__ __forceinline__ void search_body(const SearchArgs &a)
                 }
             }
         }
-        // generations (sections "Mutation and crossover", "Selection")
+        // generations (sections "Mutation and crossover", "Selection"); with
+        // ADAPT, JADE's control parameters and archive, reset per domain
+        double mu_cr = static_cast<double>(a.CR), mu_f = static_cast<double>(a.F);
+        int32_t n_arch = 0;
+        float arch[3] = {0.f, 0.f, 0.f};
         for (int32_t g = 1; g <= a.ng; ++g) {
             philox4x64_10(sid, stage, static_cast<uint64_t>(g), static_cast<uint64_t>(slot), a.seed, 0,
                           w);
             float u[3] = {0.f, 0.f, 0.f};
-            make_trial<OP>(x, S, base, np, slot, w, a.F, a.cr_thr, lo, hi, u);
+            int32_t k_cr = 0, k_f = 0, a_idx = 0;
+            if constexpr (ADAPT) {
+                uint64_t jw[4];
+                philox4x64_10(sid, stage + (1ULL << 32), static_cast<uint64_t>(g), static_cast<uint64_t>(slot),
+                              a.seed, 0, jw);
+                jade_draws(jw, mu_cr, mu_f, np, k_cr, k_f, a_idx);
+                const float F = static_cast<float>(k_f) * 0x1p-24f;
+                make_trial<OP, true>(x, S, base, np, slot, w, F, static_cast<uint64_t>(k_cr) << 8, lo, hi, u,
+                                     arch, n_arch);
+            } else {
+                make_trial<OP>(x, S, base, np, slot, w, a.F, a.cr_thr, lo, hi, u);
+            }
             const Cand<float> cand = make_cand<OP, float>(u, n0, j, ap, a.sv.nt, a.sv.dt, a.sv.dx);
             const float St = eval_slices<DT, W>(a.sv, cand, c_lo, c_hi, wave, nsl, lane, lds, buf, M);
             if (live) {
                 n_ev += 1;
                 sum_m += static_cast<uint64_t>(M);
             }
+            if constexpr (ADAPT)
+                jade_update<OP>(St >= S, x, k_cr, k_f, a_idx, grp, np, slot, arch, n_arch, mu_cr, mu_f);
             if (St >= S) {
 #pragma unroll
                 for (int d = 0; d < OP; ++d) x[d] = u[d];
@@ -692,13 +760,20 @@ __global__ __launch_bounds__(1024) void k_rms(const float *__restrict__ x, int64
 template <int OP, int DT, int W, int KIND>
 __global__ __launch_bounds__(512) void k_search(SearchArgs a)
 {
-    search_body<OP, DT, W, KIND>(a);
+    search_body<OP, DT, W, KIND, false>(a);
 }
 
 template <int OP, int DT, int W, int KIND>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_search_dense(SearchArgs a)
 {
-    search_body<OP, DT, W, KIND>(a);
+    search_body<OP, DT, W, KIND, false>(a);
+}
+
+// the same search with JADE's control-parameter adaptation and archive
+template <int OP, int DT, int W, int KIND>
+__global__ __launch_bounds__(512) void k_search_jade(SearchArgs a)
+{
+    search_body<OP, DT, W, KIND, true>(a);
 }
 
 // Gradient polish of each grid sample's winner: Adam (beta1 0.9, beta2 0.999,
@@ -819,6 +894,23 @@ __global__ __launch_bounds__(64) void k_de_trial(int32_t np, const float *__rest
     }
 }
 
+// JADE's per-slot draws for n generator blocks (a check of the device routine).
+__global__ __launch_bounds__(256) void k_jade_draws(int64_t n, const uint64_t *__restrict__ words, double mu_cr,
+                                                    double mu_f, int32_t np, int32_t *__restrict__ k_cr,
+                                                    int32_t *__restrict__ k_f, int32_t *__restrict__ a_idx)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] = words[i * 4 + k];
+    int32_t c, f, a;
+    jade_draws(w, mu_cr, mu_f, np, c, f, a);
+    k_cr[i] = c;
+    k_f[i] = f;
+    a_idx[i] = a;
+}
+
 // ---------------------------------------------------------------------------
 // launch wrappers
 
@@ -921,7 +1013,13 @@ hipError_t launch_search(int op, int dtype, int window, int kind, int dense, con
     if (n_blocks == 0) return hipSuccess;
     const size_t lds = a.nsl > 1 ? sizeof(float) * 2 * a.nsl * (window + 2) * WAVE : 0;
     const dim3 grid(static_cast<unsigned>(n_blocks)), block(WAVE * a.nsl);
-    if (kind == 0 && !dense) {
+    if (a.adapt && kind == 0) {
+        ENS_DISPATCH_OP(op, ENS_DISPATCH_DT(dtype, ENS_DISPATCH_W(window,
+            hipLaunchKernelGGL((k_search_jade<OP, DT, W, 0>), grid, block, lds, s, a))));
+    } else if (a.adapt) {
+        ENS_DISPATCH_OP(op, ENS_DISPATCH_DT(dtype, ENS_DISPATCH_W(window,
+            hipLaunchKernelGGL((k_search_jade<OP, DT, W, 1>), grid, block, lds, s, a))));
+    } else if (kind == 0 && !dense) {
         ENS_DISPATCH_OP(op, ENS_DISPATCH_DT(dtype, ENS_DISPATCH_W(window,
             hipLaunchKernelGGL((k_search<OP, DT, W, 0>), grid, block, lds, s, a))));
     } else if (kind == 0) {
@@ -980,6 +1078,15 @@ hipError_t launch_philox(int64_t n, const uint64_t *ctr, const uint64_t *key, ui
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_philox, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, ctr, key, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_jade_draws(int64_t n, const uint64_t *words, double mu_cr, double mu_f, int32_t np,
+                             int32_t *k_cr, int32_t *k_f, int32_t *a_idx, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_jade_draws, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, words, mu_cr, mu_f, np, k_cr,
+                       k_f, a_idx);
     return hipGetLastError();
 }
 

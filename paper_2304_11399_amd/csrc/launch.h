@@ -42,8 +42,9 @@ struct SearchArgs {
     int32_t plain, stage, k_begin, k_end, forward, n_bucket, ng, inject, nsl;
     int32_t xcd_order;        // 1: deal consecutive items to one XCD; 0: items in block order
     uint64_t seed;
-    float F;
+    float F, CR;              // fixed F and CR, or JADE's initial means
     uint64_t cr_thr;          // crossover draw threshold ceil(CR 2^32)
+    int32_t adapt;            // 1: JADE control-parameter adaptation and archive
     const float *Xp, *XS;     // previous stage state [n_out][n_t][P], [n_out][n_t]
     float *Yp, *YS;           // this stage's state
     unsigned long long *counters;  // [2 KIND] evaluations, [2 KIND + 1] participating traces
@@ -99,6 +100,8 @@ hipError_t launch_polish(int op, int dtype, int window, const PolishArgs &a, hip
 hipError_t launch_interp(int op, int dtype, int window, const InterpArgs &a, hipStream_t s);
 hipError_t launch_philox(int64_t n, const uint64_t *ctr, const uint64_t *key, uint64_t *out,
                          hipStream_t s);
+hipError_t launch_jade_draws(int64_t n, const uint64_t *words, double mu_cr, double mu_f, int32_t np,
+                             int32_t *k_cr, int32_t *k_f, int32_t *a_idx, hipStream_t s);
 hipError_t launch_de_trial(int32_t n_pop, int32_t np, int32_t P, const float *pop, const float *S,
                            const uint64_t *words, float F, uint64_t cr_thr, const float *lo,
                            const float *hi, float *trial, hipStream_t s);

@@ -38,7 +38,7 @@ def _ctx():
 def test_struct_sizes_match_header_layout():
     # int64 members force 8-byte alignment; the Python mirrors must agree
     assert C.sizeof(ens.Traces) == 48
-    assert C.sizeof(ens.DeCfg) == 64
+    assert C.sizeof(ens.DeCfg) == 68
     assert C.sizeof(ens.Result) == 56
     assert C.sizeof(ens.Stats) == 168
     assert C.sizeof(ens.Tuning) == 24
