@@ -550,8 +550,9 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
             }
         if (!first) continue;
         char key[256];
+        // the generation count scales every shape's time alike, so it is not part of the key
         snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d", kind, P, ctx->store_dtype, ctx->window,
-                 de->np_lo, de->np_hi, first->a.ng, first->n_blocks, n_out, n_t, ctx->ap_hi, stride);
+                 de->np_lo, de->np_hi, de->adapt, first->n_blocks, n_out, n_t, ctx->ap_hi, stride);
         int nsl = ctx->tuning.waves_per_sample_group, order = ctx->tuning.item_order;
         int dense = ctx->tuning.occupancy == 0 ? -1 : (ctx->tuning.occupancy == 2 ? 1 : 0);
         if (nsl == 0 || order == 0 || dense < 0) {
@@ -563,14 +564,12 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
             }
         }
         if (nsl == 0 || order == 0 || dense < 0) {
-            // time the first launch of this kind for every candidate shape
-            const int nsl_opts[4] = {1, 2, 4, 8};
-            std::vector<ens_ctx::Shape> cands;
-            for (int ns : nsl_opts)
-                for (int od = 1; od <= 2; ++od)
-                    for (int dn = 0; dn <= (de->adapt ? 0 : 1); ++dn)  // JADE: one register budget
-                        if ((nsl == 0 || ns == nsl) && (order == 0 || od == order) && (dense < 0 || dn == dense))
-                            cands.push_back({ns, od, dn});
+            // time the first launch of this kind: every free slice count at the
+            // first order and register budget, then the other orders and
+            // budgets at the fastest count
+            const int fixed_nsl = nsl, fixed_order = order, fixed_dense = dense;
+            const int od0 = fixed_order ? fixed_order : 1, dn0 = fixed_dense >= 0 ? fixed_dense : 0;
+            const int max_dense = de->adapt ? 0 : 1;  // JADE: one register budget
             ens::SearchArgs ta = first->a;
             if (kind == 1) {
                 HIP_OR_FAIL(ctx, hipMemsetAsync(ctx->X.p, 0, pbytes, st));
@@ -578,43 +577,54 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
                 HIP_OR_FAIL(ctx, hipMemsetAsync(ctx->Y.p, 0, pbytes, st));
                 HIP_OR_FAIL(ctx, hipMemsetAsync(ctx->YS.p, 0, sbytes, st));
             }
-            while (ctx->events.size() < 2 * cands.size()) {
+            while (ctx->events.size() < 2) {
                 hipEvent_t e;
                 HIP_OR_FAIL(ctx, hipEventCreate(&e));
                 ctx->events.push_back(e);
             }
             if (ta.progress) ta.progress = progress + n_paced;
-            for (int warm = 0; warm <= 1; ++warm) {  // load both kernel variants once
+            for (int warm = 0; warm <= max_dense; ++warm) {  // load the kernel variants once
                 if (ta.progress) HIP_OR_FAIL(ctx, hipMemsetAsync(ta.progress, 0, sizeof(unsigned long long), st));
-                ta.nsl = cands[0].nsl;
+                ta.nsl = fixed_nsl ? fixed_nsl : 1;
                 ta.xcd_order = 1;
                 ta.items = dev_items + item_off[first->item_class][1];
                 HIP_OR_FAIL(ctx, ens::launch_search(P, ctx->store_dtype, ctx->window, kind, warm, ta,
                                                     first->n_blocks, st));
             }
-            for (size_t c = 0; c < cands.size(); ++c) {
-                ta.nsl = cands[c].nsl;
-                ta.xcd_order = cands[c].order == 1;
-                ta.items = dev_items + item_off[first->item_class][cands[c].order];
-                if (ta.progress) HIP_OR_FAIL(ctx, hipMemsetAsync(ta.progress, 0, sizeof(unsigned long long), st));
-                HIP_OR_FAIL(ctx, hipEventRecord(ctx->events[2 * c], st));
-                HIP_OR_FAIL(ctx, ens::launch_search(P, ctx->store_dtype, ctx->window, kind, cands[c].dense, ta,
-                                                    first->n_blocks, st));
-                HIP_OR_FAIL(ctx, hipEventRecord(ctx->events[2 * c + 1], st));
-            }
-            HIP_OR_FAIL(ctx, hipStreamSynchronize(st));
-            float best = 0.f;
-            for (size_t c = 0; c < cands.size(); ++c) {
+            float best = -1.f;
+            auto trial = [&](int ns, int od, int dn) -> hipError_t {
+                ta.nsl = ns;
+                ta.xcd_order = od == 1;
+                ta.items = dev_items + item_off[first->item_class][od];
+                hipError_t e = hipSuccess;
+                if (ta.progress && (e = hipMemsetAsync(ta.progress, 0, sizeof(unsigned long long), st)) != hipSuccess)
+                    return e;
+                if ((e = hipEventRecord(ctx->events[0], st)) != hipSuccess) return e;
+                if ((e = ens::launch_search(P, ctx->store_dtype, ctx->window, kind, dn, ta, first->n_blocks, st)) !=
+                    hipSuccess)
+                    return e;
+                if ((e = hipEventRecord(ctx->events[1], st)) != hipSuccess) return e;
+                if ((e = hipEventSynchronize(ctx->events[1])) != hipSuccess) return e;
                 float ms = 0.f;
-                HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms, ctx->events[2 * c], ctx->events[2 * c + 1]));
+                if ((e = hipEventElapsedTime(&ms, ctx->events[0], ctx->events[1])) != hipSuccess) return e;
                 ctx->stats.tune_ms += ms;
-                if (c == 0 || ms < best) {
+                if (best < 0.f || ms < best) {
                     best = ms;
-                    nsl = cands[c].nsl;
-                    order = cands[c].order;
-                    dense = cands[c].dense;
+                    nsl = ns;
+                    order = od;
+                    dense = dn;
                 }
-            }
+                return hipSuccess;
+            };
+            const int nsl_opts[4] = {1, 2, 4, 8};
+            for (int ns : nsl_opts)
+                if (fixed_nsl == 0 || ns == fixed_nsl) HIP_OR_FAIL(ctx, trial(ns, od0, dn0));
+            const int ns_best = nsl;
+            for (int od = 1; od <= 2; ++od)
+                for (int dn = 0; dn <= max_dense; ++dn)
+                    if (!(od == od0 && dn == dn0) && (fixed_order == 0 || od == fixed_order) &&
+                        (fixed_dense < 0 || dn == fixed_dense))
+                        HIP_OR_FAIL(ctx, trial(ns_best, od, dn));
             ctx->tune_cache[key] = {nsl, order, dense};
         }
         ctx->stats.waves_used[kind] = nsl;
