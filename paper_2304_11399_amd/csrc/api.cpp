@@ -150,7 +150,9 @@ ens::StoreView view_of(const ens_ctx *c, bool master)
     ens::StoreView v{};
     const bool use_master = master && c->store_dtype != ENS_DTYPE_F32;
     v.store = use_master ? c->master.p : c->store.p;
-    v.ld = c->ld;
+    const bool half = c->store_dtype != ENS_DTYPE_F32 && !use_master;
+    v.ld = half ? 2 * c->ld : c->ld;
+    v.copy1 = half ? static_cast<int32_t>(c->ld) : 0;
     v.scale = (c->store_dtype == ENS_DTYPE_F32 || use_master) ? nullptr : c->scale.as<float>();
     v.meta = c->meta.as<TraceMeta>();
     v.cmp_ptr = c->cmp_ptr.as<int64_t>();
@@ -251,8 +253,10 @@ ens_status ens_bind(ens_ctx *ctx, const ens_traces *tr, const ens_geometry *g, c
     const int32_t nt = tr->nt;
     const int64_t ld = ((nt + 2 * PAD) + 63) / 64 * 64;
     ctx->bound = false;
-    const size_t elem = tr->store_dtype == ENS_DTYPE_F32 ? 4 : 2;
-    HIP_OR_FAIL(ctx, ctx->store.ensure(static_cast<size_t>(n_tr) * ld * elem));
+    // 16-bit rows hold two copies, the second shifted by one sample, so that
+    // every window starts on a dword boundary in one of them
+    const size_t row_bytes = tr->store_dtype == ENS_DTYPE_F32 ? 4 * ld : 2 * 2 * ld;
+    HIP_OR_FAIL(ctx, ctx->store.ensure(static_cast<size_t>(n_tr) * row_bytes));
     HIP_OR_FAIL(ctx, ctx->scale.ensure(static_cast<size_t>(n_tr) * sizeof(float)));
     if (tr->store_dtype == ENS_DTYPE_F32) {
         HIP_OR_FAIL(ctx, ens::launch_store_f32(tr->data, tr->ld, n_tr, nt, ld, ctx->store.as<float>(), ctx->stream));
@@ -260,7 +264,7 @@ ens_status ens_bind(ens_ctx *ctx, const ens_traces *tr, const ens_geometry *g, c
         HIP_OR_FAIL(ctx, ctx->master.ensure(static_cast<size_t>(n_tr) * ld * 4));
         HIP_OR_FAIL(ctx, ens::launch_store_f32(tr->data, tr->ld, n_tr, nt, ld, ctx->master.as<float>(), ctx->stream));
         HIP_OR_FAIL(ctx, ens::launch_quantize(tr->data, tr->ld, n_tr, nt, tr->store_dtype, ctx->store.as<uint16_t>(),
-                                              ld, PAD, ctx->scale.as<float>(), ctx->stream));
+                                              ld, PAD, ctx->scale.as<float>(), true, ctx->stream));
     }
     std::vector<TraceMeta> meta(static_cast<size_t>(n_tr));
     for (int32_t c = 0; c < g->n_cmp; ++c)
@@ -307,7 +311,7 @@ ens_status ens_quantize(ens_ctx *ctx, const float *data, int64_t n_traces, int32
     if (n_traces < 0 || nt < 1 || ld < nt) return fail(ctx, ENS_E_INVALID, "ens_quantize: bad sizes");
     if (dtype != ENS_DTYPE_F16 && dtype != ENS_DTYPE_BF16)
         return fail(ctx, ENS_E_INVALID, "ens_quantize: dtype must be F16 or BF16");
-    HIP_OR_FAIL(ctx, ens::launch_quantize(data, ld, n_traces, nt, dtype, q, nt, 0, scale, ctx->stream));
+    HIP_OR_FAIL(ctx, ens::launch_quantize(data, ld, n_traces, nt, dtype, q, nt, 0, scale, false, ctx->stream));
     ctx->err.clear();
     return ENS_OK;
 }

@@ -5,7 +5,9 @@
 //    samples, then zeros up to the row stride, so a window read around any
 //    participating traveltime stays inside the row and reads 0 outside the
 //    record without a bounds test; a trace that does not take part reads its
-//    window from the leading zeros, which contributes nothing.
+//    window from the leading zeros, which contributes nothing.  A 16-bit row
+//    is followed by a copy of itself shifted by one sample, so that every
+//    window is read as whole aligned dwords.
 //  - accum_trace(): traveltime of one (candidate, trace) pair, linear
 //    interpolation of the W+1 samples around it and accumulation of the
 //    window sums s_k and the energy E (section "Traveltime parameter search":
@@ -75,11 +77,12 @@ __device__ __forceinline__ float half_to_f32(uint32_t bits16, int DT)
 }
 
 // Load N (even for 16-bit storage) consecutive stored samples starting at
-// element `off` of row `row` as binary32.  16-bit rows are read as aligned
-// dwords, N/2 + 1 of them, and realigned by a funnel shift when `off` is odd.
+// element `off` of row `row` as binary32.  16-bit rows hold a second copy
+// shifted by one sample at element copy1, so a window starting at an odd
+// element is read from that copy: always N/2 aligned dwords.
 template <int DT, int N>
 __device__ __forceinline__ void load_window(const typename Store<DT>::T *__restrict__ row, uint32_t off,
-                                            float *u)
+                                            uint32_t copy1, float *u)
 {
     if constexpr (DT == DT_F32) {
         const float *p = row + off;
@@ -97,9 +100,9 @@ __device__ __forceinline__ void load_window(const typename Store<DT>::T *__restr
         if constexpr (N % 2 == 1) u[k] = p[k];
     } else {
         static_assert(N % 2 == 0, "16-bit windows hold an even number of samples");
-        constexpr int ND = N / 2 + 1;
-        const uint32_t *q = reinterpret_cast<const uint32_t *>(row + (off & ~1u));
-        const uint32_t shift = (off & 1u) << 4;
+        constexpr int ND = N / 2;
+        const uint32_t start = off + (off & 1u) * (copy1 - 1u);
+        const uint32_t *q = reinterpret_cast<const uint32_t *>(row + start);
         uint32_t d[ND];
         int k = 0;
 #pragma unroll
@@ -110,10 +113,9 @@ __device__ __forceinline__ void load_window(const typename Store<DT>::T *__restr
 #pragma unroll
         for (; k < ND; ++k) d[k] = q[k];
 #pragma unroll
-        for (int m = 0; m < N / 2; ++m) {
-            const uint32_t w = __builtin_amdgcn_alignbit(d[m + 1], d[m], shift);
-            u[2 * m] = half_to_f32(w & 0xffffu, DT);
-            u[2 * m + 1] = half_to_f32(w >> 16, DT);
+        for (int m = 0; m < ND; ++m) {
+            u[2 * m] = half_to_f32(d[m] & 0xffffu, DT);
+            u[2 * m + 1] = half_to_f32(d[m] >> 16, DT);
         }
     }
 }
@@ -266,7 +268,7 @@ __device__ __forceinline__ TT<R> traveltime(const Cand<R> &c, const CmpTerm<R> &
 template <int DT, int W, bool SCALED, typename R>
 __device__ __forceinline__ void accum_trace(Acc<W, R> &acc, const Cand<R> &c, const CmpTerm<R> &ct,
                                             R h2, const typename Store<DT>::T *__restrict__ row,
-                                            float scale)
+                                            uint32_t copy1, float scale)
 {
     const TT<R> tt = traveltime<W>(c, ct, h2);
     R wb = tt.f;
@@ -277,17 +279,17 @@ __device__ __forceinline__ void accum_trace(Acc<W, R> &acc, const Cand<R> &c, co
     }
     acc.M += tt.ok ? 1 : 0;
     float u[W + 1];
-    load_window<DT, W + 1>(row, tt.off, u);
+    load_window<DT, W + 1>(row, tt.off, copy1, u);
 #pragma unroll
     for (int k = 0; k < W; ++k) {
         // binary16 samples: two fused steps, so that they feed the
-        // mixed-precision FMA without a separate conversion; binary32: a
-        // product and one fused step (same value)
+        // mixed-precision FMA without a separate conversion (measured faster
+        // than converting first); otherwise a product and one fused step
         R a;
-        if constexpr (DT == DT_F32)
-            a = fmadd(wb, static_cast<R>(u[k + 1]), wa * static_cast<R>(u[k]));
-        else
+        if constexpr (DT == DT_F16)
             a = fmadd(wb, static_cast<R>(u[k + 1]), fmadd(wa, static_cast<R>(u[k]), R(0)));
+        else
+            a = fmadd(wb, static_cast<R>(u[k + 1]), wa * static_cast<R>(u[k]));
         acc.s[k] += a;
         acc.E = fmadd(a, a, acc.E);
     }

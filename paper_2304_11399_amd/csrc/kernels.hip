@@ -34,10 +34,12 @@ __device__ __forceinline__ uint16_t f32_to_f16_bits(float x)
 // One workgroup (256 threads) per trace: scale = max|u| (1 when the trace is
 // zero), q = RNE(u / scale).  Output row stride ld_out with the first sample
 // at column col0; when col0 > 0 the whole padded row is written.
+// dual: the row is written twice, [0, ld_out) as laid out and
+// [ld_out, 2 ld_out) shifted left by one sample (column c holds column c + 1).
 __global__ __launch_bounds__(256) void k_quantize(const float *__restrict__ src, int64_t ld_in,
                                                   int32_t nt, int32_t dtype,
                                                   uint16_t *__restrict__ dst, int64_t ld_out,
-                                                  int32_t col0, float *__restrict__ scale_out)
+                                                  int32_t col0, float *__restrict__ scale_out, int32_t dual)
 {
     __shared__ float part[256 / WAVE];
     const int64_t i = blockIdx.x;
@@ -51,10 +53,11 @@ __global__ __launch_bounds__(256) void k_quantize(const float *__restrict__ src,
     for (int w = 0; w < static_cast<int>(blockDim.x / WAVE); ++w) s = fmaxf(s, part[w]);
     if (s == 0.0f) s = 1.0f;
     if (threadIdx.x == 0) scale_out[i] = s;
-    uint16_t *out = dst + i * ld_out;
-    const int64_t row_len = col0 > 0 ? ld_out : nt;
+    uint16_t *out = dst + i * (dual ? 2 * ld_out : ld_out);
+    const int64_t row_len = dual ? 2 * ld_out : (col0 > 0 ? ld_out : nt);
     for (int64_t n = threadIdx.x; n < row_len; n += blockDim.x) {
-        const int64_t m2 = n - col0;
+        const int64_t c = n < ld_out ? n : n - ld_out + 1;
+        const int64_t m2 = c - col0;
         uint16_t q = 0;
         if (m2 >= 0 && m2 < nt) {
             const float x = row[m2] / s;
@@ -138,15 +141,15 @@ __device__ __forceinline__ void accumulate_cmps(const StoreView &sv, const Cand<
         for (; i + step < i1; i += 2 * step) {
             const int32_t i2 = i + step;
             accum_trace<DT, W, SCALED>(acc, cand, ct, h2_of<R>(meta, i),
-                                       store + static_cast<size_t>(i) * sv.ld,
+                                       store + static_cast<size_t>(i) * sv.ld, sv.copy1,
                                        SCALED ? scale[i] : 1.0f);
             accum_trace<DT, W, SCALED>(acc, cand, ct, h2_of<R>(meta, i2),
-                                       store + static_cast<size_t>(i2) * sv.ld,
+                                       store + static_cast<size_t>(i2) * sv.ld, sv.copy1,
                                        SCALED ? scale[i2] : 1.0f);
         }
         if (i < i1)
             accum_trace<DT, W, SCALED>(acc, cand, ct, h2_of<R>(meta, i),
-                                       store + static_cast<size_t>(i) * sv.ld,
+                                       store + static_cast<size_t>(i) * sv.ld, sv.copy1,
                                        SCALED ? scale[i] : 1.0f);
     }
 }
@@ -252,7 +255,7 @@ __device__ __forceinline__ float semblance_grad_lane(const StoreView &sv, const 
             const bool use = nonzero && tt.ok && tt.tau > 0.0f;
             const float sc = scale ? scale[i] : 1.0f;
             float u[W + 1];
-            load_window<DT, W + 1>(store + static_cast<size_t>(i) * sv.ld, tt.off, u);
+            load_window<DT, W + 1>(store + static_cast<size_t>(i) * sv.ld, tt.off, sv.copy1, u);
             const float wa = (1.0f - tt.f) * sc, wb = tt.f * sc;
             float dSdtau = 0.0f;
 #pragma unroll
@@ -956,11 +959,11 @@ hipError_t launch_store_f32(const float *src, int64_t ld_in, int64_t n_tr, int32
 }
 
 hipError_t launch_quantize(const float *src, int64_t ld_in, int64_t n_tr, int32_t nt, int32_t dtype,
-                           uint16_t *dst, int64_t ld_out, int32_t col0, float *scale, hipStream_t s)
+                           uint16_t *dst, int64_t ld_out, int32_t col0, float *scale, bool dual, hipStream_t s)
 {
     if (n_tr == 0) return hipSuccess;
     hipLaunchKernelGGL(k_quantize, dim3(static_cast<unsigned>(n_tr)), dim3(256), 0, s, src, ld_in, nt,
-                       dtype, dst, ld_out, col0, scale);
+                       dtype, dst, ld_out, col0, scale, static_cast<int32_t>(dual));
     return hipGetLastError();
 }
 

@@ -11,7 +11,8 @@ struct TraceMeta;
 // Bound trace store and per-time tables.
 struct StoreView {
     const void *store;        // [n_tr][ld] padded rows, sample 0 at column PAD
-    int64_t ld;
+    int64_t ld;               // row stride in elements
+    int32_t copy1;            // 16-bit rows: element offset of the copy shifted by one sample (else 0)
     const float *scale;       // [n_tr] per-trace scale, or nullptr for binary32 storage
     const TraceMeta *meta;    // [n_tr]
     const int64_t *cmp_ptr;   // [n_cmp+1]
@@ -79,8 +80,9 @@ struct PolishArgs {
 // launch wrappers (return hipSuccess or the launch error)
 hipError_t launch_store_f32(const float *src, int64_t ld_in, int64_t n_tr, int32_t nt, int64_t ld,
                             float *dst, hipStream_t s);
+// dual: each output row is two rows of ld_out, the second shifted by one sample
 hipError_t launch_quantize(const float *src, int64_t ld_in, int64_t n_tr, int32_t nt, int32_t dtype,
-                           uint16_t *dst, int64_t ld_out, int32_t col0, float *scale,
+                           uint16_t *dst, int64_t ld_out, int32_t col0, float *scale, bool dual,
                            hipStream_t s);
 hipError_t launch_eval(int op, int dtype, int window, const StoreView &sv, const CandView &cv,
                        float *S, int32_t *M, hipStream_t s);
