@@ -1,0 +1,80 @@
+"""Full-size workloads on the GPU, checked on sampled outputs the oracle
+computes one by one: the uneven batch (NP 16 to 64, aperture 2 to 16), the
+binary16 / bfloat16 storage line and the binary16 + polish line, each in the
+launch configuration the benchmark times (one fixed shape here, so that no
+shape-measuring launches are needed)."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2304_11399_amd.counts import evals_ens
+from synth import base_bounds, make_workload
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+TOL_S = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ens():
+    import paper_2304_11399_amd as e
+    assert torch.cuda.is_available()
+    return e
+
+
+def _expected_evals(de, g):
+    if de["np_lo"] == de["np_hi"]:
+        return evals_ens(g.n_cmp * g.nt, de["np_lo"], de["ng_f"], de["np_bf"], de["ng_bf"],
+                         de["n_cycle"], 0)
+    first = sum(oracle.pop_size(de, g.nt, t) * (1 + de["ng_f"]) for t in range(g.nt))
+    return g.n_cmp * (first + de["n_cycle"] * g.nt * 2 * (de["np_bf"] * (1 + de["ng_bf"]) - 1))
+
+
+def _gap(name, S64, g):
+    ref = np.load(os.path.join(ROOT, "tests", "golden", f"sref_{name}.npz"))
+    fp = float((g.traces.astype(np.float64) ** 2).sum())
+    assert abs(fp / float(ref["fingerprint"]) - 1.0) < 1e-9, "reference maxima made for other data"
+    found = S64.reshape(-1)[ref["cmp"].astype(np.int64) * g.nt + ref["t"]]
+    return np.maximum(ref["S_ref"] - found, 0.0)
+
+
+@pytest.mark.parametrize("name,store", [("crs_uneven", "f32"), ("crs_precision", "f16"),
+                                        ("crs_precision", "bf16"), ("crs_diff", "f16")])
+def test_full_size_workload(ens, name, store):
+    g, wl = make_workload(name)
+    ctx = ens.Context()
+    ctx.bind(torch.from_numpy(g.traces).cuda(), g.cmp_ptr, g.offset, g.dt, g.dx, wl["op"],
+             wl["window"], wl["ap_lo"], wl["ap_hi"], store=store)
+    ctx.set_tuning(waves_per_sample_group=4, item_order=1, occupancy=1)
+    de = wl["de"]
+    out = ctx.search(base_bounds(wl), de, seed=wl["search_seed"], keep_pre_polish=True)
+    assert out["n_evals"] == _expected_evals(de, g)
+    P_d = g.n_cmp * g.nt
+    pick = np.sort(np.random.default_rng(3).choice(P_d, 1500, replace=False))
+    cmp, t = (pick // g.nt).astype(np.int32), (pick % g.nt).astype(np.int32)
+    p = out["params"].cpu().numpy().reshape(-1, 3)[pick].astype(np.float64)
+    S = out["S"].cpu().numpy().reshape(-1)[pick]
+    traces = None
+    if store != "f32":
+        q, s = oracle.quantize(g.traces, store)
+        traces = oracle.dequantize(q, s, store)
+    Lq = oracle.Line.from_gather(g, wl["window"], wl["op"], wl["ap_lo"], wl["ap_hi"], traces=traces)
+    S_q, _, margin = Lq.semblance(cmp, t, p)
+    err = np.abs(S - S_q)[margin >= 0.05]
+    del Lq
+    L32 = oracle.Line.from_gather(g, wl["window"], wl["op"], wl["ap_lo"], wl["ap_hi"])
+    S_32, _, margin32 = L32.semblance(cmp, t, p)
+    S64 = out["S64"].cpu().numpy()
+    err64 = np.abs(S64.reshape(-1)[pick] - S_32)[margin32 > 1e-6]
+    gap = _gap(name, S64, g)
+    print(f"{name} {store}: max|S - S_oracle(stored)| {err.max():.2e}; max|S64 - S_oracle| "
+          f"{err64.max():.2e}; mean gap {gap.mean():.2e} ({np.mean(gap <= 1e-3):.3f} <= 1e-3)")
+    assert err.max() <= TOL_S
+    assert err64.max() < 1e-11
+    assert gap.mean() <= 1e-3
+    if de.get("polish_steps", 0) > 0:
+        assert torch.all(out["S"] >= out["S_pre_polish"])
