@@ -81,24 +81,34 @@ def cpu_baseline(g, wl, de, bounds):
     import oracle
     L = oracle.Line.from_gather(g, wl["window"], wl["op"], wl["ap_lo"], wl["ap_hi"])
     if wl["de"]["ens_enabled"]:
-        mid = g.n_cmp // 2
-        cmp_out = np.arange(mid - 2, mid + 2, dtype=np.int32)
+        # successive 4-CMP buckets from the middle of the line, t over the
+        # middle half of the record, until at least 10 s of work
+        mid = g.n_cmp // 2 - 2
         t0, t1 = g.nt // 4, g.nt // 4 + min(500, g.nt // 2)
         de_s = dict(de, n_bucket=4)
-        what = f"ENS over CMPs {cmp_out[0]}..{cmp_out[-1]} (one 4-CMP bucket) x t {t0}..{t1 - 1}"
     else:
-        cmp_out = np.arange(g.n_cmp, dtype=np.int32)
         t0, t1 = 0, g.nt
         de_s = de
-        what = "plain DE over the whole line, repeated for at least 10 s"
     start = time.perf_counter()
     n = ev = 0
+    k = 0
     while True:
+        if wl["de"]["ens_enabled"]:
+            c0 = (mid + 4 * k) % max(1, g.n_cmp - 3)
+            cmp_out = np.arange(c0, c0 + 4, dtype=np.int32)
+        else:
+            cmp_out = np.arange(g.n_cmp, dtype=np.int32)
         _, _, e = L.search(bounds, de_s, wl["search_seed"], cmp_out=cmp_out, t_begin=t0, t_end=t1)
         n += cmp_out.size * (t1 - t0)
         ev += e
-        if wl["de"]["ens_enabled"] or time.perf_counter() - start >= 10.0:
+        k += 1
+        if time.perf_counter() - start >= 10.0:
             break
+    if wl["de"]["ens_enabled"]:
+        what = (f"ENS over {k} 4-CMP bucket(s) from CMP {mid} on x t {t0}..{t1 - 1}, "
+                f"at least 10 s")
+    else:
+        what = f"plain DE over the whole line, {k} time(s), at least 10 s"
     sec = time.perf_counter() - start
     threads = oracle.lib().or_num_threads()
     return {"value": round(n / sec, 3), "unit": "ZO samples/s", "cores": int(threads),
