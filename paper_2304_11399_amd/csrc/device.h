@@ -66,52 +66,61 @@ __device__ __forceinline__ float f16_bits_to_f32(uint32_t b)
     return static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(b)));
 }
 
-typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
-typedef float f2u __attribute__((ext_vector_type(2), aligned(4)));
-
-typedef uint32_t u4u __attribute__((ext_vector_type(4), aligned(4)));
+typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ float half_to_f32(uint32_t bits16, int DT)
 {
     return DT == DT_F16 ? f16_bits_to_f32(bits16) : bf16_bits_to_f32(bits16);
 }
 
+// Raw buffer view of one padded trace row (wave-uniform, so it lives in
+// scalar registers); a read past row_bytes returns zeros.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_buffer(const void *row, uint32_t row_bytes)
+{
+    // word 3: 32-bit data format, no swizzle, no stride (the gfx9 raw-buffer setting)
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(row), static_cast<short>(0),
+                                             static_cast<int>(row_bytes), 0x00020000);
+}
+
 // Load N (even for 16-bit storage) consecutive stored samples starting at
-// element `off` of row `row` as binary32.  16-bit rows hold a second copy
-// shifted by one sample at element copy1, so a window starting at an odd
-// element is read from that copy: always N/2 aligned dwords.
+// byte `off` of row `row` (row_bytes long) as binary32.  16-bit rows hold a
+// second copy shifted by one sample at element copy1, so a window starting
+// at an odd element is read from that copy (element copy1 + off/2 - 1):
+// always N/2 aligned dwords.  The loads are raw buffer loads with the row in
+// scalar registers and a 32-bit lane offset.
 template <int DT, int N>
 __device__ __forceinline__ void load_window(const typename Store<DT>::T *__restrict__ row, uint32_t off,
-                                            uint32_t copy1, float *u)
+                                            uint32_t copy1, uint32_t row_bytes, float *u)
 {
+    const __amdgpu_buffer_rsrc_t rs = row_buffer(row, row_bytes);
     if constexpr (DT == DT_F32) {
-        const float *p = row + off;
         int k = 0;
 #pragma unroll
         for (; k + 4 <= N; k += 4) {
-            f4u v = *reinterpret_cast<const f4u *>(p + k);
-            u[k] = v.x; u[k + 1] = v.y; u[k + 2] = v.z; u[k + 3] = v.w;
+            const u4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 4u * k, 0, 0);
+            u[k] = __uint_as_float(v.x); u[k + 1] = __uint_as_float(v.y);
+            u[k + 2] = __uint_as_float(v.z); u[k + 3] = __uint_as_float(v.w);
         }
         if constexpr (N % 4 >= 2) {
-            f2u v = *reinterpret_cast<const f2u *>(p + k);
-            u[k] = v.x; u[k + 1] = v.y;
+            const u2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, off + 4u * k, 0, 0);
+            u[k] = __uint_as_float(v.x); u[k + 1] = __uint_as_float(v.y);
             k += 2;
         }
-        if constexpr (N % 2 == 1) u[k] = p[k];
+        if constexpr (N % 2 == 1) u[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, off + 4u * k, 0, 0));
     } else {
         static_assert(N % 2 == 0, "16-bit windows hold an even number of samples");
         constexpr int ND = N / 2;
-        const uint32_t start = off + (off & 1u) * (copy1 - 1u);
-        const uint32_t *q = reinterpret_cast<const uint32_t *>(row + start);
+        const uint32_t start = off + (off & 2u) * (copy1 - 1u);
         uint32_t d[ND];
         int k = 0;
 #pragma unroll
         for (; k + 4 <= ND; k += 4) {
-            const u4u v = *reinterpret_cast<const u4u *>(q + k);
+            const u4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, start + 4u * k, 0, 0);
             d[k] = v.x; d[k + 1] = v.y; d[k + 2] = v.z; d[k + 3] = v.w;
         }
 #pragma unroll
-        for (; k < ND; ++k) d[k] = q[k];
+        for (; k < ND; ++k) d[k] = __builtin_amdgcn_raw_buffer_load_b32(rs, start + 4u * k, 0, 0);
 #pragma unroll
         for (int m = 0; m < ND; ++m) {
             u[2 * m] = half_to_f32(d[m] & 0xffffu, DT);
@@ -201,9 +210,12 @@ __device__ __forceinline__ float fmadd(float a, float b, float c) { return __bui
 __device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float floor_r(float x) { return __builtin_floorf(x); }
 __device__ __forceinline__ double floor_r(double x) { return __builtin_floor(x); }
-// Clamp into [-1e30, 1e30] (keeps the fraction of a far-off traveltime finite).
-__device__ __forceinline__ float clamp_big(float x) { return __builtin_amdgcn_fmed3f(x, -1e30f, 1e30f); }
-__device__ __forceinline__ double clamp_big(double x) { return __builtin_fmin(__builtin_fmax(x, -1e30), 1e30); }
+// Clamp into [lo, hi]; a NaN gives a bound, which differs from the NaN.
+__device__ __forceinline__ float clamp_to(float x, float lo, float hi) { return __builtin_amdgcn_fmed3f(x, lo, hi); }
+__device__ __forceinline__ double clamp_to(double x, double lo, double hi)
+{
+    return __builtin_fmin(__builtin_fmax(x, lo), hi);
+}
 
 __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -232,9 +244,9 @@ __device__ __forceinline__ CmpTerm<R> cmp_term(const Cand<R> &cand, int32_t c, R
 
 // Traveltime of (candidate, trace) in sample units.  q = n0^2 + mo < 0 (no
 // real traveltime) fails the range test, as does any trace outside the
-// candidate's aperture.  off: column of the
-// window's first sample in the padded row, or 0 (a run of zero padding) for
-// a trace that does not take part.
+// candidate's aperture.  off: byte offset of the window's first sample in the
+// padded row of ESZ-byte elements, or 0 (a run of zero padding) for a trace
+// that does not take part.
 template <typename R>
 struct TT {
     bool ok;
@@ -243,34 +255,51 @@ struct TT {
     R tau;        // sqrt(q) in samples
 };
 
-template <int W, typename R>
+template <int W, int ESZ, typename R>
 __device__ __forceinline__ TT<R> traveltime(const Cand<R> &c, const CmpTerm<R> &ct, R h2)
 {
+    static_assert(ESZ == 2 || ESZ == 4, "2- or 4-byte samples");
     TT<R> r;
     const R mo = fmadd(c.ga, h2, ct.part);
     const R q = c.n0sq + mo;
-    // q < 0: the square root is NaN, the guarded denominator 1e-30 and the
-    // clamped dtau -1e30 (mo < -n0^2 <= 0), below every range
+    // q < 0: the square root is NaN, the guarded denominator 1e-30 and dtau
+    // a large negative number (mo < -n0^2 <= 0), below every range
     const R tau = fast_sqrt(q);
     const R s = tau + c.n0f;
     const R den = s > R(1e-30) ? s : R(1e-30);
-    const R dtau = clamp_big(mo * fast_rcp(den));
-    r.ok = ct.in_ap && (dtau >= c.lo_lim) && (dtau <= c.hi_lim);
-    const R fl = floor_r(dtau);
-    r.f = dtau - fl;
-    const int32_t col = c.n0 + static_cast<int32_t>(fl) + (PAD - W / 2);
-    r.off = r.ok ? static_cast<uint32_t>(col) : 0u;
+    const R dtau = mo * fast_rcp(den);
+    // participation -n0 <= dtau <= nt-1-n0: the clamped value equals dtau
+    // exactly when dtau lies in the range; the clamped value keeps the
+    // fraction and the window column finite for every trace
+    const R dc = clamp_to(dtau, c.lo_lim, c.hi_lim);
+    r.ok = ct.in_ap && dc == dtau;
+    const R fl = floor_r(dc);
+    r.f = dc - fl;
+    uint32_t off;
+    if constexpr (sizeof(R) == 4) {
+        // column n0 + fl + PAD - W/2 lies in [0, nt + PAD) with nt <= 2^20:
+        // adding it to 1.5 * 2^23 is exact and gives the bit pattern
+        // 0x4B400000 + column, so the column needs no float-to-integer
+        // conversion (the constant part is per candidate)
+        const float K = c.n0f + (12582912.0f + static_cast<float>(PAD - W / 2));
+        const uint32_t bits = __float_as_uint(fl + K);
+        off = bits * ESZ - 0x4B400000u * ESZ;
+    } else {
+        off = static_cast<uint32_t>(c.n0 + static_cast<int32_t>(fl) + (PAD - W / 2)) * ESZ;
+    }
+    r.off = r.ok ? off : 0u;
     r.tau = tau;
     return r;
 }
 
-// Accumulate one trace into the window sums.  row: the padded trace row.
+// Accumulate one trace into the window sums.  row: the padded trace row,
+// row_bytes long.
 template <int DT, int W, bool SCALED, typename R>
 __device__ __forceinline__ void accum_trace(Acc<W, R> &acc, const Cand<R> &c, const CmpTerm<R> &ct,
                                             R h2, const typename Store<DT>::T *__restrict__ row,
-                                            uint32_t copy1, float scale)
+                                            uint32_t copy1, uint32_t row_bytes, float scale)
 {
-    const TT<R> tt = traveltime<W>(c, ct, h2);
+    const TT<R> tt = traveltime<W, sizeof(typename Store<DT>::T)>(c, ct, h2);
     R wb = tt.f;
     R wa = R(1) - tt.f;
     if constexpr (SCALED) {
@@ -279,14 +308,18 @@ __device__ __forceinline__ void accum_trace(Acc<W, R> &acc, const Cand<R> &c, co
     }
     acc.M += tt.ok ? 1 : 0;
     float u[W + 1];
-    load_window<DT, W + 1>(row, tt.off, copy1, u);
+    load_window<DT, W + 1>(row, tt.off, copy1, row_bytes, u);
 #pragma unroll
     for (int k = 0; k < W; ++k) {
-        // binary16 samples: two fused steps, so that they feed the
-        // mixed-precision FMA without a separate conversion (measured faster
-        // than converting first); otherwise a product and one fused step
+        // binary32 samples in binary32: u_k + f (u_k+1 - u_k), a difference
+        // and one fused step, with no separate 1 - f; binary16 samples: two
+        // fused steps, so that they feed the mixed-precision FMA without a
+        // separate conversion (measured faster than converting first);
+        // otherwise a product and one fused step
         R a;
-        if constexpr (DT == DT_F16)
+        if constexpr (DT == DT_F32 && !SCALED && sizeof(R) == 4)
+            a = fmadd(tt.f, u[k + 1] - u[k], u[k]);
+        else if constexpr (DT == DT_F16)
             a = fmadd(wb, static_cast<R>(u[k + 1]), fmadd(wa, static_cast<R>(u[k]), R(0)));
         else
             a = fmadd(wb, static_cast<R>(u[k + 1]), wa * static_cast<R>(u[k]));

@@ -134,6 +134,7 @@ __device__ __forceinline__ void accumulate_cmps(const StoreView &sv, const Cand<
     const ENS_CONST_AS TraceMeta *meta = const_view(sv.meta);
     const ENS_CONST_AS float *scale = const_view(sv.scale);
     const R dx = static_cast<R>(sv.dx);
+    const uint32_t row_bytes = static_cast<uint32_t>(sv.ld * static_cast<int64_t>(sizeof(T)));
     for (int32_t c = c_lo; c <= c_hi; ++c) {
         const CmpTerm<R> ct = cmp_term(cand, c, dx);
         const int32_t i1 = static_cast<int32_t>(cmp_ptr[c + 1]);
@@ -141,15 +142,15 @@ __device__ __forceinline__ void accumulate_cmps(const StoreView &sv, const Cand<
         for (; i + step < i1; i += 2 * step) {
             const int32_t i2 = i + step;
             accum_trace<DT, W, SCALED>(acc, cand, ct, h2_of<R>(meta, i),
-                                       store + static_cast<size_t>(i) * sv.ld, sv.copy1,
+                                       store + static_cast<size_t>(i) * sv.ld, sv.copy1, row_bytes,
                                        SCALED ? scale[i] : 1.0f);
             accum_trace<DT, W, SCALED>(acc, cand, ct, h2_of<R>(meta, i2),
-                                       store + static_cast<size_t>(i2) * sv.ld, sv.copy1,
+                                       store + static_cast<size_t>(i2) * sv.ld, sv.copy1, row_bytes,
                                        SCALED ? scale[i2] : 1.0f);
         }
         if (i < i1)
             accum_trace<DT, W, SCALED>(acc, cand, ct, h2_of<R>(meta, i),
-                                       store + static_cast<size_t>(i) * sv.ld, sv.copy1,
+                                       store + static_cast<size_t>(i) * sv.ld, sv.copy1, row_bytes,
                                        SCALED ? scale[i] : 1.0f);
     }
 }
@@ -251,11 +252,12 @@ __device__ __forceinline__ float semblance_grad_lane(const StoreView &sv, const 
         const int32_t i1 = static_cast<int32_t>(cmp_ptr[c + 1]);
         for (int32_t i = static_cast<int32_t>(cmp_ptr[c]); i < i1; ++i) {
             const float h2 = meta[i].h2;
-            const TT<float> tt = traveltime<W>(cand, ct, h2);
+            const TT<float> tt = traveltime<W, sizeof(T)>(cand, ct, h2);
             const bool use = nonzero && tt.ok && tt.tau > 0.0f;
             const float sc = scale ? scale[i] : 1.0f;
             float u[W + 1];
-            load_window<DT, W + 1>(store + static_cast<size_t>(i) * sv.ld, tt.off, sv.copy1, u);
+            load_window<DT, W + 1>(store + static_cast<size_t>(i) * sv.ld, tt.off, sv.copy1,
+                                   static_cast<uint32_t>(sv.ld * static_cast<int64_t>(sizeof(T))), u);
             const float wa = (1.0f - tt.f) * sc, wb = tt.f * sc;
             float dSdtau = 0.0f;
 #pragma unroll
@@ -729,10 +731,11 @@ __global__ __launch_bounds__(256) void k_stack(StoreView sv, const int32_t *__re
         const CmpTerm<float> ct = cmp_term(cand, cm, sv.dx);
         const int32_t i1 = static_cast<int32_t>(cmp_ptr[cm + 1]);
         for (int32_t i = static_cast<int32_t>(cmp_ptr[cm]); i < i1; ++i) {
-            // a one-sample window: off is the column of the sample before the traveltime
-            const TT<float> tt = traveltime<1>(cand, ct, meta[i].h2);
+            // a one-sample window: off is the byte offset of the sample before the traveltime
+            const TT<float> tt = traveltime<1, 4>(cand, ct, meta[i].h2);
             const float *row = store + static_cast<size_t>(i) * sv.ld;
-            const float u0 = row[tt.off], u1 = row[tt.off + 1];
+            const float *p0 = reinterpret_cast<const float *>(reinterpret_cast<const char *>(row) + tt.off);
+            const float u0 = p0[0], u1 = p0[1];
             sum += fmadd(tt.f, u1, (1.0f - tt.f) * u0);
             M += tt.ok ? 1 : 0;
         }
