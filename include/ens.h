@@ -201,7 +201,7 @@ typedef struct {
     int32_t collect_timing;          /* 1: time every search launch with HIP events */
     int32_t item_order;              /* 0: measure; 1: XCD-contiguous (bucket, t) order;
                                         2: costliest items first, dealt round-robin */
-    int32_t occupancy;               /* 0: measure; 1: registers as compiled (5 waves per SIMD);
+    int32_t occupancy;               /* 0: measure; 1: registers as compiled (4 waves per SIMD);
                                         2: held to 64 registers (8 waves per SIMD) */
 } ens_tuning;
 
