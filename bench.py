@@ -213,7 +213,7 @@ def gap_stats(name, S64, nt, g):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        msg = ("this build runs on one GPU only: the search shards by bucket across GPUs "
+        msg = ("the library runs on one GPU: the search shards by bucket across GPUs "
                "by design but no multi-GPU path is built; run with --gpus 1")
         print(json.dumps({"metric": METRIC, "error": msg, "n_gpus": args.gpus}))
         sys.exit(2)

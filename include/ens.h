@@ -55,7 +55,7 @@ typedef enum {
                                n_skip outside 0..2 or without ENS, index out of range */
     ENS_E_HIP = -3,         /* a HIP runtime call failed (message has the HIP error string) */
     ENS_E_OOM = -4,         /* device allocation failed */
-    ENS_E_UNSUPPORTED = -5, /* valid request this build does not implement */
+    ENS_E_UNSUPPORTED = -5, /* valid request the library does not implement */
     ENS_E_STATE = -6        /* call needs ens_bind first */
 } ens_status;
 
