@@ -1,6 +1,7 @@
 """GPU search with the options combined, against the oracle: JADE with time
 skipping, JADE on binary16 traces, the CMP operator with JADE and skipping,
-bfloat16 traces, then the polish.  Counts exact, reported scores within the
+bfloat16 traces, then the polish; graph replay of JADE with skipping on
+binary16 traces.  Counts exact, reported scores within the
 semblance tolerance of the oracle's score of the same parameters, search
 quality close to the oracle's own run."""
 import numpy as np
@@ -95,3 +96,32 @@ def test_bfloat16_traces_then_polish(ens):
     err = np.abs(out["S"].cpu().numpy().reshape(-1) - S_or)[margin >= 0.05]
     print(f"bf16 polished: max|S - S_oracle(p)| {err.max():.2e}")
     assert err.max() <= TOL_S
+
+
+def test_jade_graph_replay_on_binary16_matches_eager(ens):
+    g, wl = make_workload("crs_ens", n_cmp=12, nt=200)
+    de = dict(wl["de"], np_lo=16, np_hi=16, ng_f=6, n_bucket=6, adapt=1, CR=0.5, n_skip=1)
+    bounds = base_bounds(wl)
+
+    def make(stream=None):
+        c = ens.Context(stream)
+        c.bind(torch.from_numpy(g.traces).cuda(), g.cmp_ptr, g.offset, g.dt, g.dx, wl["op"],
+               wl["window"], wl["ap_lo"], wl["ap_hi"], store="f16")
+        return c
+
+    eager = make()
+    eager.set_tuning(waves_per_sample_group=2, item_order=1)
+    ref = eager.search(bounds, de, seed=19)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        gctx = make(s)
+        gctx.set_tuning(waves_per_sample_group=2, item_order=1, use_graph=1)
+        for rep in range(3):
+            out = gctx.search(bounds, de, seed=19)
+            torch.cuda.synchronize()
+            assert torch.equal(out["params"], ref["params"]), rep
+            assert torch.equal(out["S"], ref["S"]), rep
+            assert out["n_evals"] == ref["n_evals"]
+            # unrelated eager work between replays
+            x = torch.randn(1 << 20, device="cuda")
+            (x * 2).sum().item()
