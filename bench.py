@@ -67,7 +67,8 @@ def parse():
     ap.add_argument("--store", default=None, help="f32, f16 or bf16 (default: the workload's)")
     ap.add_argument("--waves", type=int, default=0, help="trace slices per population (0: auto)")
     ap.add_argument("--order", type=int, default=0,
-                    help="work-item order: 1 XCD-contiguous, 2 costliest first (0: measure)")
+                    help="work-item order: 1 XCD-contiguous, 2 costliest first, "
+                         "3 costliest first within XCD-contiguous shares (0: measure)")
     ap.add_argument("--occupancy", type=int, default=0,
                     help="search kernel registers: 1 as compiled, 2 held to 64 (0: measure)")
     ap.add_argument("--graph", action="store_true", help="replay the trace steps as a HIP graph")

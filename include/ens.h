@@ -200,7 +200,8 @@ typedef struct {
     int32_t use_graph;               /* 1: replay the trace-step launches as a HIP graph */
     int32_t collect_timing;          /* 1: time every search launch with HIP events */
     int32_t item_order;              /* 0: measure; 1: XCD-contiguous (bucket, t) order;
-                                        2: costliest items first, dealt round-robin */
+                                        2: costliest items first, dealt round-robin;
+                                        3: XCD-contiguous shares, costliest first in each */
     int32_t occupancy;               /* 0: measure; 1: registers as compiled (4 waves per SIMD);
                                         2: held to 64 registers (8 waves per SIMD) */
 } ens_tuning;

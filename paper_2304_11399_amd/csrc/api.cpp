@@ -202,8 +202,8 @@ ens_status ens_set_tuning(ens_ctx *ctx, const ens_tuning *t)
         return fail(ctx, ENS_E_RANGE, "waves_per_sample_group must be 0, 1, 2, 4 or 8 (got %d)", w);
     if (t->use_graph && t->collect_timing)
         return fail(ctx, ENS_E_INVALID, "use_graph and collect_timing exclude each other");
-    if (t->item_order < 0 || t->item_order > 2)
-        return fail(ctx, ENS_E_RANGE, "item_order must be 0, 1 or 2 (got %d)", t->item_order);
+    if (t->item_order < 0 || t->item_order > 3)
+        return fail(ctx, ENS_E_RANGE, "item_order must be 0, 1, 2 or 3 (got %d)", t->item_order);
     if (t->occupancy < 0 || t->occupancy > 2)
         return fail(ctx, ENS_E_RANGE, "occupancy must be 0, 1 or 2 (got %d)", t->occupancy);
     ctx->tuning = *t;
@@ -369,7 +369,10 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
     for (int32_t o = 0; o < n_out; ++o) cmp_out[o] = grid->cmp_out ? grid->cmp_out[o] : o;
 
     // work items: consecutive t with equal NP packed floor(64/NP) per wave, in
-    // (group, t) order; the second copy puts the costliest items first
+    // (group, t) order (order 1); the second copy puts the costliest items
+    // first (order 2); the third keeps each XCD's contiguous share of the
+    // (group, t) order and puts the costliest items of that share first
+    // (order 3)
     const double traces_per_cmp = static_cast<double>(ctx->n_tr) / ctx->n_cmp;
     // item classes: 0 = first sweep (NP_f), 1 = backward sweeps, 2 = later
     // forward sweeps (NP_bf); each estimates t = t_begin + init + m stride
@@ -401,18 +404,31 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
         std::stable_sort(v.begin(), v.end(), [&](const int4 &x, const int4 &y) { return cost(x) > cost(y); });
         return v;
     };
+    // the share of XCD x under the block remapping of the kernels (xcd_remap)
+    auto xcd_costliest_first = [&](const std::vector<int4> &items) {
+        std::vector<int4> v = items;
+        const size_t n = v.size(), per = n / 8, rem = n % 8;
+        for (size_t x = 0; x < 8; ++x) {
+            const size_t b = x * per + std::min(x, rem), e = b + per + (x < rem ? 1 : 0);
+            std::vector<int4> part(v.begin() + b, v.begin() + e);
+            part = costliest_first(part);
+            std::copy(part.begin(), part.end(), v.begin() + b);
+        }
+        return v;
+    };
     const bool ens = de->ens_enabled != 0;
     const int32_t n_buckets = ens ? (n_out + de->n_bucket - 1) / de->n_bucket : 0;
-    std::vector<int4> cls_items[3][3];  // [class][order 1, 2 at index 1, 2]
+    std::vector<int4> cls_items[3][4];  // [class][order 1, 2, 3 at index 1, 2, 3]
     build_items(ens ? n_buckets : n_out, 0, cls_items[0][1]);
     if (ens && de->n_cycle > 0) {
         build_items(n_buckets, 1, cls_items[1][1]);
         build_items(n_buckets, 2, cls_items[2][1]);
     }
-    size_t item_off[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, n_items_total = 0;
+    size_t item_off[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}}, n_items_total = 0;
     for (int c = 0; c < 3; ++c) {
         cls_items[c][2] = costliest_first(cls_items[c][1]);
-        for (int od = 1; od <= 2; ++od) {
+        cls_items[c][3] = xcd_costliest_first(cls_items[c][1]);
+        for (int od = 1; od <= 3; ++od) {
             item_off[c][od] = n_items_total;
             n_items_total += cls_items[c][od].size();
         }
@@ -435,7 +451,7 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
                                     hipMemcpyHostToDevice, st));
     int4 *dev_items = ctx->items.as<int4>();
     for (int c = 0; c < 3; ++c)
-        for (int od = 1; od <= 2; ++od)
+        for (int od = 1; od <= 3; ++od)
             if (!cls_items[c][od].empty())
                 HIP_OR_FAIL(ctx, hipMemcpyAsync(dev_items + item_off[c][od], cls_items[c][od].data(),
                                                 cls_items[c][od].size() * sizeof(int4), hipMemcpyHostToDevice, st));
@@ -598,7 +614,7 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
             float best = -1.f;
             auto trial = [&](int ns, int od, int dn) -> hipError_t {
                 ta.nsl = ns;
-                ta.xcd_order = od == 1;
+                ta.xcd_order = od != 2;
                 ta.items = dev_items + item_off[first->item_class][od];
                 hipError_t e = hipSuccess;
                 if (ta.progress && (e = hipMemsetAsync(ta.progress, 0, sizeof(unsigned long long), st)) != hipSuccess)
@@ -624,7 +640,7 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
             for (int ns : nsl_opts)
                 if (fixed_nsl == 0 || ns == fixed_nsl) HIP_OR_FAIL(ctx, trial(ns, od0, dn0));
             const int ns_best = nsl;
-            for (int od = 1; od <= 2; ++od)
+            for (int od = 1; od <= 3; ++od)
                 for (int dn = 0; dn <= max_dense; ++dn)
                     if (!(od == od0 && dn == dn0) && (fixed_order == 0 || od == fixed_order) &&
                         (fixed_dense < 0 || dn == fixed_dense))
@@ -637,7 +653,7 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
         for (auto &l : seq)
             if (l.kind == kind && !l.interp) {
                 l.a.nsl = nsl;
-                l.a.xcd_order = order == 1;
+                l.a.xcd_order = order != 2;
                 l.a.items = dev_items + item_off[l.item_class][order];
                 l.dense = dense;
             }

@@ -30,11 +30,12 @@ def test_item_order_does_not_change_results(ens):
     ctx = _ctx(ens, g, wl)
     de = dict(wl["de"], ng_f=5, n_bucket=8)
     outs = []
-    for order in (1, 2):
+    for order in (1, 2, 3):
         ctx.set_tuning(waves_per_sample_group=2, item_order=order)
         outs.append(ctx.search(base_bounds(wl), de, seed=4))
-    assert torch.equal(outs[0]["params"], outs[1]["params"])
-    assert torch.equal(outs[0]["S"], outs[1]["S"])
+    for o in outs[1:]:
+        assert torch.equal(outs[0]["params"], o["params"])
+        assert torch.equal(outs[0]["S"], o["S"])
 
 
 def test_measured_launch_shape_is_reused_and_reproducible(ens):
@@ -45,7 +46,7 @@ def test_measured_launch_shape_is_reused_and_reproducible(ens):
     st = ctx.stats()
     assert st["tune_ms"] > 0
     w, o = st["explore"]["waves"], st["explore"]["item_order"]
-    assert w in (1, 2, 4, 8) and o in (1, 2)
+    assert w in (1, 2, 4, 8) and o in (1, 2, 3)
     b = ctx.search(base_bounds(wl), de, seed=2)
     assert ctx.stats()["tune_ms"] == 0  # cached
     assert torch.equal(a["params"], b["params"])
