@@ -191,9 +191,10 @@ typedef struct {
 /* Search-kernel launch shape.  Zero fields are chosen by measurement: the
  * first search of a given shape times its first launch of each kernel kind,
  * first for every slice count (1, 2, 4, 8) at the first free item order and
- * register budget, then for the other orders and budgets at the fastest count,
- * and keeps the fastest for later searches of that shape on the same context
- * (the generation count does not enter the shape). */
+ * register budget, then for the other orders and budgets at the fastest count
+ * (a launch under 5 ms timed three times, the fastest counting), and keeps the
+ * fastest for later searches of that shape on the same context (the
+ * generation count does not enter the shape). */
 typedef struct {
     uint32_t struct_size;
     int32_t waves_per_sample_group;  /* trace slices per population (1, 2, 4, 8); 0: measure */
