@@ -82,6 +82,12 @@ def lib():
         L.or_stack_batch.argtypes = [C.POINTER(_Line), C.c_int64, P, P, P, P, P]
         L.or_jade_draws.argtypes = [P, C.c_double, C.c_double, C.c_int32, P, P, P]
         L.or_jade_trial.argtypes = [C.c_int32, C.c_int32, P, P, P, C.c_int32, P, P, P, P, P, P]
+        for name in ("or_jade_ln", "or_jade_cos_turns", "or_jade_tan_half_turn"):
+            getattr(L, name).argtypes = [C.c_double]
+            getattr(L, name).restype = C.c_double
+        L.or_jade_series_batch.argtypes = [C.c_int32, C.c_int64, P, P]
+        L.or_jade_run.argtypes = [C.c_int32, C.c_int32, P, P, C.c_int32, P, P, P, P, C.c_float,
+                                  C.c_float, P, P, P, P, P, P]
         L.or_rms.argtypes = [P, C.c_int64]
         L.or_rms.restype = C.c_double
         _lib = L
@@ -265,6 +271,43 @@ def jade_draws(words, mu_cr, mu_f, np_):
                             C.byref(one_f), C.byref(one_a))
         k_cr[i], k_f[i], a_idx[i] = one_cr.value, one_f.value, one_a.value
     return k_cr, k_f, a_idx
+
+
+def jade_series(name, x):
+    """The oracle's written-out series ('ln', 'cos_turns' or 'tan_half_turn')
+    at every point of x (binary64)."""
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1)
+    y = np.zeros_like(x)
+    which = {"ln": 0, "cos_turns": 1, "tan_half_turn": 2}[name]
+    lib().or_jade_series_batch(which, x.size, _ptr(x), _ptr(y))
+    return y
+
+
+def jade_run(pop, S, de_words, St, F0, CR0, lo, hi, jade_words=None, draws=None):
+    """ng JADE generations of one population with explicit generator words and
+    trial scores (see or_jade_run).  Returns the final (pop, S) and per
+    generation the trials, (mu_CR, mu_F), archive sizes and archives."""
+    pop = np.ascontiguousarray(pop, dtype=np.float32).copy()
+    np_, P = pop.shape
+    S = np.ascontiguousarray(S, dtype=np.float64).copy()
+    de_words = np.ascontiguousarray(de_words, dtype=np.uint64).reshape(-1, np_, 4)
+    ng = de_words.shape[0]
+    St = np.ascontiguousarray(St, dtype=np.float64).reshape(ng, np_)
+    if jade_words is not None:
+        jade_words = np.ascontiguousarray(jade_words, dtype=np.uint64).reshape(ng, np_, 4)
+    else:
+        draws = np.ascontiguousarray(draws, dtype=np.int32).reshape(ng, np_, 3)
+    lo = np.ascontiguousarray(lo, dtype=np.float32)
+    hi = np.ascontiguousarray(hi, dtype=np.float32)
+    trials = np.zeros((ng, np_, P), np.float32)
+    mu = np.zeros((ng, 2))
+    n_arch = np.zeros(ng, np.int32)
+    arch = np.zeros((ng, np_, P), np.float32)
+    lib().or_jade_run(np_, P, _ptr(pop), _ptr(S), ng, _ptr(de_words),
+                      None if jade_words is None else _ptr(jade_words),
+                      None if draws is None else _ptr(draws), _ptr(St), float(F0), float(CR0),
+                      _ptr(lo), _ptr(hi), _ptr(trials), _ptr(mu), _ptr(n_arch), _ptr(arch))
+    return dict(pop=pop, S=S, trials=trials, mu=mu, n_arch=n_arch, archive=arch)
 
 
 def jade_trial(pop, S, archive, words, k_f, k_cr, lo, hi):

@@ -91,6 +91,27 @@ void or_de_trial(int32_t np, int32_t P, const float *pop, const double *S, const
 void or_jade_draws(const uint64_t w[4], double mu_cr, double mu_f, int32_t np, int32_t *k_cr,
                    int32_t *k_f, int32_t *a_idx);
 
+/* The written-out binary64 series the JADE draws use: ln u (u > 0),
+ * cos(2 pi t) for t in [0, 1) and tan(pi x) for x in (-1/2, 1/2). */
+double or_jade_ln(double u);
+double or_jade_cos_turns(double t);
+double or_jade_tan_half_turn(double x);
+/* y[i] = series which (0 ln, 1 cos_turns, 2 tan_half_turn) at x[i]. */
+void or_jade_series_batch(int32_t which, int64_t n, const double *x, double *y);
+
+/* ng JADE generations of one population of np members with explicit inputs,
+ * through the same selection, archive and mean-update steps as the search:
+ * pop [np][P], S [np] (in/out); de_words [ng][np][4] the slots' DE blocks;
+ * the draws come from jade_words [ng][np][4] at the current means, or, when
+ * jade_words is NULL, are given as draws [ng][np][3] = (k_cr, k_f, a_idx);
+ * St [ng][np] the trial scores.  Initial means CR0, F0 and an empty archive.
+ * Per generation: trials_out [ng][np][P], mu_out [ng][2] = (mu_CR, mu_F)
+ * after its update, n_arch_out [ng] and archive_out [ng][np][P]. */
+void or_jade_run(int32_t np, int32_t P, float *pop, double *S, int32_t ng, const uint64_t *de_words,
+                 const uint64_t *jade_words, const int32_t *draws, const double *St, float F0, float CR0,
+                 const float *lo, const float *hi, float *trials_out, double *mu_out, int32_t *n_arch_out,
+                 float *archive_out);
+
 /* One JADE generation's trial vectors: current-to-best/1 with the second
  * difference vector drawn from population plus archive (archive: [n_arch][P]),
  * per-slot F = k_f / 2^24 and CR = k_cr / 2^24; words: the slots' DE blocks. */

@@ -234,6 +234,16 @@ static double jade_tan_half_turn(double x)
     return x < 0.0 ? -t : t;
 }
 
+double or_jade_ln(double u) { return jade_ln(u); }
+double or_jade_cos_turns(double t) { return jade_cos_turns(t); }
+double or_jade_tan_half_turn(double x) { return jade_tan_half_turn(x); }
+
+void or_jade_series_batch(int32_t which, int64_t n, const double *x, double *y)
+{
+    for (int64_t i = 0; i < n; ++i)
+        y[i] = which == 0 ? jade_ln(x[i]) : (which == 1 ? jade_cos_turns(x[i]) : jade_tan_half_turn(x[i]));
+}
+
 void or_jade_draws(const uint64_t w[4], double mu_cr, double mu_f, int32_t np, int32_t *k_cr,
                    int32_t *k_f, int32_t *a_idx)
 {
@@ -343,6 +353,65 @@ static double objective(const objective_ctx *o, int32_t j, int32_t n0, const flo
     return inside;
 }
 
+/* JADE's state of one domain: the control-parameter means and the archive
+ * of replaced parents. */
+typedef struct {
+    double mu_cr, mu_f;
+    int32_t n_arch;
+    float archive[MAXNP * 3];
+} jade_state;
+
+/* Synchronous selection after a generation's trials are scored (section
+ * "Selection"): trial i replaces parent i when St[i] >= S[i].  With JADE's
+ * adaptation, in slot order every replaced parent enters the archive
+ * (appended while it holds fewer than np entries, else at that slot's drawn
+ * position a_idx[i]) and the slot's CR and F join the successful sets; then,
+ * if any slot succeeded, mu_CR moves 10% toward the arithmetic mean of the
+ * successful CR and mu_F 10% toward the Lehmer mean (sum F^2 / sum F) of the
+ * successful F.  CR and F are k / 2^24, so the sums are exact integers. */
+static void select_and_adapt(int np, int P, int adapt, const float *trial, const double *St, float *pop,
+                             double *S, const int32_t *k_cr, const int32_t *k_f, const int32_t *a_idx,
+                             jade_state *js)
+{
+    int64_t n_succ = 0, sum_cr = 0, sum_f = 0, sum_f2 = 0;
+    for (int i = 0; i < np; ++i) {
+        if (St[i] >= S[i]) {
+            if (adapt) {
+                float *dst = js->n_arch < np ? js->archive + (js->n_arch++) * P : js->archive + a_idx[i] * P;
+                memcpy(dst, pop + i * P, sizeof(float) * (size_t)P);
+                n_succ += 1;
+                sum_cr += k_cr[i];
+                sum_f += k_f[i];
+                sum_f2 += (int64_t)k_f[i] * k_f[i];
+            }
+            memcpy(pop + i * P, trial + i * P, sizeof(float) * (size_t)P);
+            S[i] = St[i];
+        }
+    }
+    if (adapt && n_succ > 0) {
+        const double mean_cr = (double)sum_cr / ((double)n_succ * JADE_GRID);
+        const double lehmer_f = (double)sum_f2 / ((double)sum_f * JADE_GRID);
+        js->mu_cr = 0.9 * js->mu_cr + 0.1 * mean_cr;
+        js->mu_f = 0.9 * js->mu_f + 0.1 * lehmer_f;
+    }
+}
+
+/* Trial vectors of one generation: fixed F and CR, or JADE's per-slot draws
+ * (from the slots' adaptation blocks jw at the current means) with the
+ * archive feeding x_r2. */
+static void make_trials(int np, int P, int adapt, float F, float CR, const float *pop, const double *S,
+                        const uint64_t *words, const uint64_t *jw, const float *lo, const float *hi,
+                        jade_state *js, int32_t *k_cr, int32_t *k_f, int32_t *a_idx, float *trial)
+{
+    if (adapt) {
+        for (int i = 0; i < np; ++i)
+            or_jade_draws(jw + 4 * i, js->mu_cr, js->mu_f, np, &k_cr[i], &k_f[i], &a_idx[i]);
+        or_jade_trial(np, P, pop, S, js->archive, js->n_arch, words, k_f, k_cr, lo, hi, trial);
+    } else {
+        or_de_trial(np, P, pop, S, words, F, CR, lo, hi, trial);
+    }
+}
+
 /* NG generations of DE on one domain; pop/S hold the scored initial
  * population on entry and the final one on exit.  Returns evaluations. */
 static int64_t evolve(const objective_ctx *o, uint64_t seed, uint64_t sample, uint64_t stage,
@@ -352,52 +421,64 @@ static int64_t evolve(const objective_ctx *o, uint64_t seed, uint64_t sample, ui
     const int P = o->P;
     float trial[MAXNP * 3];
     double St[MAXNP];
-    uint64_t words[MAXNP * 4];
+    uint64_t words[MAXNP * 4], jw[MAXNP * 4];
     int64_t evals = 0;
     const int adapt = o->cfg->adapt;
-    double mu_cr = (double)o->cfg->CR, mu_f = (double)o->cfg->F;
-    float archive[MAXNP * 3];
-    int32_t n_arch = 0, k_cr[MAXNP], k_f[MAXNP], a_idx[MAXNP];
+    jade_state js;
+    js.mu_cr = (double)o->cfg->CR;
+    js.mu_f = (double)o->cfg->F;
+    js.n_arch = 0;
+    int32_t k_cr[MAXNP], k_f[MAXNP], a_idx[MAXNP];
     for (int g = 1; g <= ng; ++g) {
-        for (int i = 0; i < np; ++i)
+        for (int i = 0; i < np; ++i) {
             rng_words(seed, sample, stage, (uint64_t)g, (uint64_t)i, words + 4 * i);
-        if (adapt) {
-            for (int i = 0; i < np; ++i) {
-                uint64_t jw[4];
-                rng_words(seed, sample, stage + (1ULL << 32), (uint64_t)g, (uint64_t)i, jw);
-                or_jade_draws(jw, mu_cr, mu_f, np, &k_cr[i], &k_f[i], &a_idx[i]);
-            }
-            or_jade_trial(np, P, pop, S, archive, n_arch, words, k_f, k_cr, lo, hi, trial);
-        } else {
-            or_de_trial(np, P, pop, S, words, o->cfg->F, o->cfg->CR, lo, hi, trial);
+            if (adapt)
+                rng_words(seed, sample, stage + (1ULL << 32), (uint64_t)g, (uint64_t)i, jw + 4 * i);
         }
+        make_trials(np, P, adapt, o->cfg->F, o->cfg->CR, pop, S, words, jw, lo, hi, &js, k_cr, k_f, a_idx,
+                    trial);
         for (int i = 0; i < np; ++i) {
             St[i] = objective(o, j, n0, trial + i * P, lo, hi);
             ++evals;
         }
-        int64_t n_succ = 0, sum_cr = 0, sum_f = 0, sum_f2 = 0;
-        for (int i = 0; i < np; ++i) {
-            if (St[i] >= S[i]) {
-                if (adapt) {
-                    float *dst = n_arch < np ? archive + (n_arch++) * P : archive + a_idx[i] * P;
-                    memcpy(dst, pop + i * P, sizeof(float) * (size_t)P);
-                    n_succ += 1;
-                    sum_cr += k_cr[i];
-                    sum_f += k_f[i];
-                    sum_f2 += (int64_t)k_f[i] * k_f[i];
-                }
-                memcpy(pop + i * P, trial + i * P, sizeof(float) * (size_t)P);
-                S[i] = St[i];
-            }
-        }
-        if (adapt && n_succ > 0) {
-            const double mean_cr = (double)sum_cr / ((double)n_succ * JADE_GRID);
-            const double lehmer_f = (double)sum_f2 / ((double)sum_f * JADE_GRID);
-            mu_cr = 0.9 * mu_cr + 0.1 * mean_cr;
-            mu_f = 0.9 * mu_f + 0.1 * lehmer_f;
-        }
+        select_and_adapt(np, P, adapt, trial, St, pop, S, k_cr, k_f, a_idx, &js);
     }
     return evals;
+}
+
+void or_jade_run(int32_t np, int32_t P, float *pop, double *S, int32_t ng, const uint64_t *de_words,
+                 const uint64_t *jade_words, const int32_t *draws, const double *St, float F0, float CR0,
+                 const float *lo, const float *hi, float *trials_out, double *mu_out, int32_t *n_arch_out,
+                 float *archive_out)
+{
+    jade_state js;
+    js.mu_cr = (double)CR0;
+    js.mu_f = (double)F0;
+    js.n_arch = 0;
+    memset(js.archive, 0, sizeof js.archive);
+    int32_t k_cr[MAXNP], k_f[MAXNP], a_idx[MAXNP];
+    for (int32_t g = 0; g < ng; ++g) {
+        const uint64_t *w = de_words + (size_t)g * np * 4;
+        if (jade_words) {
+            make_trials(np, P, 1, F0, CR0, pop, S, w, jade_words + (size_t)g * np * 4, lo, hi, &js, k_cr, k_f,
+                        a_idx, trials_out + (size_t)g * np * P);
+        } else {
+            for (int32_t i = 0; i < np; ++i) {
+                const int32_t *d = draws + ((size_t)g * np + i) * 3;
+                k_cr[i] = d[0];
+                k_f[i] = d[1];
+                a_idx[i] = d[2];
+            }
+            or_jade_trial(np, P, pop, S, js.archive, js.n_arch, w, k_f, k_cr, lo, hi,
+                          trials_out + (size_t)g * np * P);
+        }
+        select_and_adapt(np, P, 1, trials_out + (size_t)g * np * P, St + (size_t)g * np, pop, S, k_cr, k_f,
+                         a_idx, &js);
+        mu_out[2 * g] = js.mu_cr;
+        mu_out[2 * g + 1] = js.mu_f;
+        n_arch_out[g] = js.n_arch;
+        memcpy(archive_out + (size_t)g * np * P, js.archive, sizeof(float) * (size_t)np * P);
+    }
 }
 
 static int best_index(const double *S, int np)
