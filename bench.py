@@ -2,15 +2,19 @@
 """Throughput of the ENS traveltime-parameter search on one MI355X.
 
 One step = one pass of the whole path over the workload: bind the
-device-resident traces into the library's store, then the search (initial
-populations, every generation of every ENS stage, the neighbour exchange) and
-the binary64 re-scoring of every winner.  Prints one JSON line.
+device-resident traces into the library's store (quantising them to binary16
+for the 16-bit workloads), then the search (initial populations, every
+generation of every ENS stage, the neighbour exchange), the gradient polish
+where the workload has one, and the binary64 re-scoring of every winner.
+Prints one JSON line.
 
-Workloads (synthetic Ricker gathers, synth.WORKLOADS): crs_ens (default:
-256 CMPs x 48 offsets x 1000 samples, CRS operator, NP 32 x NG 80 + ENS),
-cmp_small, crs_uneven, crs_precision, crs_diff.
+Workloads (synthetic Ricker gathers, synth.WORKLOADS): crs_diff (default:
+2048 CMPs x 96 offsets x 2000 samples at 2 ms, CRS operator, NP 32 x NG 40 +
+ENS, binary16 traces, 10 adjoint-polish steps), crs_ens, cmp_small,
+crs_uneven, crs_precision.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,7 +30,10 @@ FP32_PEAK_TFLOPS = 157.3       # MI355X vector binary32 (counts packed dual-FMA 
 # 256 CUs at 2.4 GHz; derived from unit counts, matching the ~60 B per busy
 # cycle the TA counters show for the search kernel's window loads
 VMEM_PATH_PEAK_GBS = 256 * 64 * 2.4
-CU, CLOCK_GHZ = 256, 2.4
+CSRC = os.path.join(ROOT, "paper_2304_11399_amd", "csrc")
+KERNEL_SOURCES = ("device.h", "eval.h", "launch.h", "search.h", "kernels.hip", "search_f32.hip",
+                  "search_f16.hip", "search_bf16.hip")
+DT_CODE = {"f32": 0, "f16": 1, "bf16": 2}
 
 
 def flops_per_pair(op, window):
@@ -42,18 +49,25 @@ def flops_per_pair(op, window):
     return tt + 6 * window + 1
 
 
-def measured_traffic(workload):
-    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    counter summary, or None when the kernel sources changed since then."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", f"{workload}_traffic.json")
+def kernel_sources_sha(root=ROOT):
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(root, "paper_2304_11399_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def measured_profile(workload, kernel, shape, root=ROOT):
+    """The committed rocprofv3 summary of the dominant kernel (HBM bytes per
+    launch from FETCH_SIZE/WRITE_SIZE, VALU/TA busy, L2 hit rate), or None when
+    the kernel sources, the kernel or its launch shape differ from the
+    profiled ones."""
+    path = os.path.join(root, "profiles", f"{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    h = hashlib.sha256()
-    for f in ("device.h", "kernels.hip"):
-        h.update(open(os.path.join(ROOT, "paper_2304_11399_amd", "csrc", f), "rb").read())
-    if h.hexdigest() != rec["source_sha256"]:
+    if rec.get("source_sha256") != kernel_sources_sha(root) or rec.get("kernel") != kernel:
+        return None
+    if rec.get("shape") != shape:
         return None
     return rec
 
@@ -63,7 +77,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="crs_ens")
+    ap.add_argument("--workload", default="crs_diff")
     ap.add_argument("--store", default=None, help="f32, f16 or bf16 (default: the workload's)")
     ap.add_argument("--waves", type=int, default=0, help="trace slices per population (0: auto)")
     ap.add_argument("--order", type=int, default=0,
@@ -73,93 +87,122 @@ def parse():
                     help="search kernel registers: 1 as compiled, 2 held to 64 (0: measure)")
     ap.add_argument("--graph", action="store_true", help="replay the trace steps as a HIP graph")
     ap.add_argument("--no-compare", action="store_true",
-                    help="skip the equal-accuracy comparison of ENS with plain per-sample DE")
+                    help="skip the equal-accuracy comparison of the variants")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gap", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=8.0,
+                    help="CPU work per oracle timing (all cores, then one core)")
     return ap.parse_args()
 
 
-def cpu_baseline(g, wl, de, bounds):
-    """The oracle (binary64 C, OpenMP) on a bounded sample of the workload."""
+def cpu_baseline(g, wl, de, bounds, seconds):
+    """The oracle (binary64 C, OpenMP) on a bounded sample of the workload, on
+    every host core it is given and on one core."""
     import numpy as np
 
     import oracle
     L = oracle.Line.from_gather(g, wl["window"], wl["op"], wl["ap_lo"], wl["ap_hi"])
     if wl["de"]["ens_enabled"]:
-        # successive 4-CMP buckets from the middle of the line, t over the
-        # middle half of the record, until at least 10 s of work
         mid = g.n_cmp // 2 - 2
         t0, t1 = g.nt // 4, g.nt // 4 + min(500, g.nt // 2)
-        de_s = dict(de, n_bucket=4)
+        de_s = dict(de, n_bucket=4, polish_steps=0)
     else:
         t0, t1 = 0, g.nt
         de_s = de
-    start = time.perf_counter()
-    n = ev = 0
-    k = 0
-    while True:
-        if wl["de"]["ens_enabled"]:
-            c0 = (mid + 4 * k) % max(1, g.n_cmp - 3)
-            cmp_out = np.arange(c0, c0 + 4, dtype=np.int32)
-        else:
-            cmp_out = np.arange(g.n_cmp, dtype=np.int32)
-        _, _, e = L.search(bounds, de_s, wl["search_seed"], cmp_out=cmp_out, t_begin=t0, t_end=t1)
-        n += cmp_out.size * (t1 - t0)
-        ev += e
-        k += 1
-        if time.perf_counter() - start >= 10.0:
-            break
+
+    def timed(limit):
+        start = time.perf_counter()
+        n = ev = k = 0
+        while True:
+            if wl["de"]["ens_enabled"]:
+                # successive 4-CMP buckets from the middle of the line
+                c0 = (mid + 4 * k) % max(1, g.n_cmp - 3)
+                cmp_out = np.arange(c0, c0 + 4, dtype=np.int32)
+                tt1 = t1
+            else:
+                cmp_out = np.arange(g.n_cmp, dtype=np.int32)
+                tt1 = t1
+            _, _, e = L.search(bounds, de_s, wl["search_seed"], cmp_out=cmp_out, t_begin=t0,
+                               t_end=tt1)
+            n += cmp_out.size * (tt1 - t0)
+            ev += e
+            k += 1
+            if time.perf_counter() - start >= limit:
+                break
+        return n, ev, k, time.perf_counter() - start
+
+    lib = oracle.lib()
+    threads = int(lib.or_num_threads())
+    n, ev, k, sec = timed(seconds)
+    lib.or_set_num_threads(1)
     if wl["de"]["ens_enabled"]:
-        what = (f"ENS over {k} 4-CMP bucket(s) from CMP {mid} on x t {t0}..{t1 - 1}, "
-                f"at least 10 s")
+        t1_all = t1
+        t1 = t0 + min(100, t1 - t0)     # a narrower band of t keeps the one-core leg short
+    n1, ev1, k1, sec1 = timed(seconds)
+    lib.or_set_num_threads(threads)
+    if wl["de"]["ens_enabled"]:
+        what = (f"ENS (no polish) over {k} 4-CMP bucket(s) from CMP {mid} x t {t0}..{t1_all - 1}")
+        what1 = f"{k1} 4-CMP bucket(s) x t {t0}..{t1 - 1}"
     else:
-        what = f"plain DE over the whole line, {k} time(s), at least 10 s"
-    sec = time.perf_counter() - start
-    threads = oracle.lib().or_num_threads()
-    return {"value": round(n / sec, 3), "unit": "ZO samples/s", "cores": int(threads),
-            "kind": "oracle", "sample": f"{what}: {n} ZO samples, {ev} evaluations, "
-            f"{sec:.1f} s, {ev / sec:.4g} evals/s"}
+        what, what1 = f"plain DE over the whole line, {k} time(s)", f"{k1} time(s)"
+    return {"value": round(n / sec, 3), "unit": "ZO samples/s", "cores": threads, "kind": "oracle",
+            "sample": f"{what}: {n} ZO samples, {ev} evaluations, {sec:.1f} s, {ev / sec:.4g} evals/s",
+            "one_core": {"value": round(n1 / sec1, 3), "unit": "ZO samples/s", "cores": 1,
+                         "sample": f"{what1}: {n1} ZO samples, {ev1} evaluations, {sec1:.1f} s, "
+                                   f"{ev1 / sec1:.4g} evals/s"}}
 
 
-def compare_equal_accuracy(ctx, ctx_plain, bounds, wl, store, g, seed):
-    """ENS (without and with the paper's N_skip = 2 time skipping, with fixed F
-    and CR and with JADE's adaptation; the workload's storage and polish)
-    against the per-sample search the paper compares with (binary32 storage,
-    no polish), each over a few budgets: the fastest budget whose mean gap to
-    the reference maxima is <= 1e-3 is each method's throughput at that
-    accuracy."""
-    import torch
+def variants_for(name, wl):
+    """(method, storage, search configuration) rows of the equal-accuracy
+    comparison.  crs_diff: the spec claim, the binary16 search with the
+    adjoint polish against the per-sample binary32 search the paper compares
+    with, with ENS in binary32 and in binary16 without polish between them."""
     de0 = dict(wl["de"])
     plain0 = dict(de0, ens_enabled=0, polish_steps=0, n_skip=0)
-    variants = [("ens", dict(de0)),
-                ("ens", dict(de0, np_lo=16, np_hi=16, ng_f=20)),
-                ("ens", dict(de0, np_lo=16, np_hi=16, ng_f=10)),
-                ("ens", dict(de0, np_lo=8, np_hi=8, ng_f=8)),
-                ("ens_skip2", dict(de0, n_skip=2)),
-                ("ens_skip2", dict(de0, np_lo=16, np_hi=16, ng_f=20, n_skip=2)),
-                ("ens_skip2", dict(de0, np_lo=16, np_hi=16, ng_f=10, n_skip=2)),
-                ("ens_jade", dict(de0, adapt=1, CR=0.5)),
-                ("ens_jade", dict(de0, np_lo=16, np_hi=16, ng_f=20, adapt=1, CR=0.5)),
-                ("ens_jade", dict(de0, np_lo=16, np_hi=16, ng_f=10, adapt=1, CR=0.5)),
-                ("plain_jade", dict(plain0, np_lo=16, np_hi=16, ng_f=20, adapt=1, CR=0.5)),
-                ("plain_jade", dict(plain0, ng_f=40, adapt=1, CR=0.5)),
-                ("plain_jade", dict(plain0, adapt=1, CR=0.5)),
-                ("plain", dict(plain0, np_lo=16, np_hi=16, ng_f=20)),
-                ("plain", dict(plain0, ng_f=40)),
-                ("plain", dict(plain0)),
-                ("plain", dict(plain0, ng_f=2 * plain0["ng_f"]))]
-    if not wl["de"]["ens_enabled"]:
-        return None
-    seen, unique = set(), []
-    for kind, de in variants:
-        key = (kind, tuple(sorted(de.items())))
-        if key not in seen:
-            seen.add(key)
-            unique.append((kind, de))
-    variants = unique
+    if name == "crs_diff":
+        nop = dict(de0, polish_steps=0)
+        return [("ens_f16_polish", "f16", dict(de0)),
+                ("ens_f16_polish", "f16", dict(de0, np_lo=16, np_hi=16, ng_f=20)),
+                ("ens_f16_polish", "f16", dict(de0, np_lo=16, np_hi=16, ng_f=10)),
+                ("ens_f16", "f16", dict(nop)),
+                ("ens_f16", "f16", dict(nop, np_lo=16, np_hi=16, ng_f=20)),
+                ("ens_f32", "f32", dict(nop)),
+                ("ens_f32", "f32", dict(nop, np_lo=16, np_hi=16, ng_f=20)),
+                ("plain_f32", "f32", dict(plain0, np_lo=16, np_hi=16, ng_f=20)),
+                ("plain_f32", "f32", dict(plain0)),
+                ("plain_f32", "f32", dict(plain0, ng_f=80))]
+    if name == "crs_ens":
+        return [("ens", "f32", dict(de0)),
+                ("ens", "f32", dict(de0, np_lo=16, np_hi=16, ng_f=20)),
+                ("ens", "f32", dict(de0, np_lo=16, np_hi=16, ng_f=10)),
+                ("ens_skip2", "f32", dict(de0, n_skip=2)),
+                ("ens_skip2", "f32", dict(de0, np_lo=16, np_hi=16, ng_f=20, n_skip=2)),
+                ("ens_jade", "f32", dict(de0, adapt=1, CR=0.5)),
+                ("ens_jade", "f32", dict(de0, np_lo=16, np_hi=16, ng_f=20, adapt=1, CR=0.5)),
+                ("plain_jade", "f32", dict(plain0, ng_f=40, adapt=1, CR=0.5)),
+                ("plain_jade", "f32", dict(plain0, adapt=1, CR=0.5)),
+                ("plain", "f32", dict(plain0, np_lo=16, np_hi=16, ng_f=20)),
+                ("plain", "f32", dict(plain0, ng_f=40)),
+                ("plain", "f32", dict(plain0))]
+    if name == "cmp_small":
+        # the configured budget is NP 16 x NG 30; more generations do not close
+        # the gap (the populations settle on side maxima), a larger population does
+        return [("plain", "f32", dict(de0)),
+                ("plain", "f32", dict(de0, ng_f=60)),
+                ("plain", "f32", dict(de0, np_lo=24, np_hi=24, ng_f=20)),
+                ("plain", "f32", dict(de0, np_lo=24, np_hi=24))]
+    return []
+
+
+def compare_equal_accuracy(ctxs, bounds, wl, g, seed, note):
+    """Each row's throughput and gap; the fastest row of each method whose mean
+    gap to the reference maxima is <= 1e-3 is that method's throughput at
+    equal accuracy."""
+    import torch
     rows = []
-    for k, (kind, de) in enumerate(variants):
-        c = ctx_plain if kind.startswith("plain") else ctx
+    variants = variants_for(wl["name"], wl)
+    for k, (kind, store, de) in enumerate(variants):
+        c = ctxs[store]
         for attempt in range(2):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -169,11 +212,10 @@ def compare_equal_accuracy(ctx, ctx_plain, bounds, wl, store, g, seed):
             if c.stats()["tune_ms"] == 0:  # no launch-shape measurement inside the clock
                 break
         gap = gap_stats(wl["name"], out["S64"].cpu().numpy(), g.nt, g)
-        print(f"bench: compare {k + 1}/{len(variants)} {kind} {de['np_lo']}x{de['ng_f']}: "
-              f"{1e3 * sec:.1f} ms", file=sys.stderr, flush=True)
+        note(f"compare {k + 1}/{len(variants)} {kind} {de['np_lo']}x{de['ng_f']}: {1e3 * sec:.1f} ms")
         rows.append({"method": kind, "np": de["np_lo"], "ng": de["ng_f"],
                      "n_skip": de.get("n_skip", 0), "adapt": de.get("adapt", 0),
-                     "store": store if c is ctx else "f32", "polish": de.get("polish_steps", 0),
+                     "store": store, "polish": de.get("polish_steps", 0),
                      "ms": round(1e3 * sec, 2), "zo_samples_per_s": round(g.n_cmp * g.nt / sec, 1),
                      "evals": out["n_evals"], "gap_mean": gap["mean"] if gap else None,
                      "frac_le_1e-3": gap["frac_le_1e-3"] if gap else None})
@@ -188,10 +230,17 @@ def compare_equal_accuracy(ctx, ctx_plain, bounds, wl, store, g, seed):
         if a in best and b in best:
             return round(best[a]["zo_samples_per_s"] / best[b]["zo_samples_per_s"], 3)
         return None
-    return {"store": store, "runs": rows, "best_at_gap_le_1e-3": best,
-            "ens_over_plain_zo_samples_per_s": ratio("ens", "plain"),
-            "ens_skip2_over_plain_zo_samples_per_s": ratio("ens_skip2", "plain"),
-            "ens_jade_over_plain_jade_zo_samples_per_s": ratio("ens_jade", "plain_jade")}
+    res = {"runs": rows, "best_at_gap_le_1e-3": best}
+    if wl["name"] == "crs_diff":
+        res["ens_f16_polish_over_plain_f32_zo_samples_per_s"] = ratio("ens_f16_polish", "plain_f32")
+        res["ens_f16_over_plain_f32"] = ratio("ens_f16", "plain_f32")
+        res["ens_f32_over_plain_f32"] = ratio("ens_f32", "plain_f32")
+        res["ens_f16_polish_over_ens_f32"] = ratio("ens_f16_polish", "ens_f32")
+    elif wl["name"] == "crs_ens":
+        res["ens_over_plain_zo_samples_per_s"] = ratio("ens", "plain")
+        res["ens_skip2_over_plain_zo_samples_per_s"] = ratio("ens_skip2", "plain")
+        res["ens_jade_over_plain_jade_zo_samples_per_s"] = ratio("ens_jade", "plain_jade")
+    return res
 
 
 def gap_stats(name, S64, nt, g):
@@ -225,8 +274,12 @@ def main():
     import paper_2304_11399_amd as ens
     from synth import base_bounds, make_workload
 
+    def note(msg):
+        print(f"bench: {msg}", file=sys.stderr, flush=True)
+
     torch.cuda.set_device(0)
     g, wl = make_workload(args.workload)
+    wl = dict(wl, name=args.workload)
     store = args.store or wl["store"]
     de, bounds = dict(wl["de"]), base_bounds(wl)
     stream = torch.cuda.Stream() if args.graph else torch.cuda.current_stream()
@@ -234,21 +287,30 @@ def main():
         ctx = ens.Context(stream)
         ctx.set_tuning(waves_per_sample_group=args.waves, use_graph=int(args.graph),
                        item_order=args.order, occupancy=args.occupancy)
+        # the one-time host-to-device upload, outside the steps
+        torch.cuda.synchronize()
+        t_up = time.perf_counter()
         traces = torch.from_numpy(g.traces).cuda()
+        torch.cuda.synchronize()
+        upload_ms = 1e3 * (time.perf_counter() - t_up)
         P_d = g.n_cmp * g.nt
 
-        def step():
+        def bind():
             ctx.bind(traces, g.cmp_ptr, g.offset, g.dt, g.dx, wl["op"], wl["window"], wl["ap_lo"],
                      wl["ap_hi"], store=store)
-            return ctx.search(bounds, de, wl["search_seed"], rescore_fp64=True)
 
-        def note(msg):
-            print(f"bench: {msg}", file=sys.stderr, flush=True)
+        def step():
+            bind()
+            return ctx.search(bounds, de, wl["search_seed"], rescore_fp64=True)
 
         note(f"{args.workload}: {args.warmup} warm-up step(s), launch shapes measured in the first")
         for _ in range(args.warmup):
             out = step()
         torch.cuda.synchronize()
+        t_b = time.perf_counter()
+        bind()
+        torch.cuda.synchronize()
+        bind_ms = 1e3 * (time.perf_counter() - t_b)
         note(f"warm-up done; timing {args.steps} step(s)")
         t0 = time.perf_counter()
         for _ in range(args.steps):
@@ -276,14 +338,14 @@ def main():
         stack_info = {"ms": round(stack_ms, 3), "coherence_rms": round(coherence_rms, 6),
                       "stack_rms": round(float(stack.double().pow(2).mean().sqrt().item()), 6)}
         comparison = None
-        if not args.no_compare and not args.no_gap:
-            ctx_plain = ctx
-            if store != "f32":
-                ctx_plain = ens.Context(stream)
-                ctx_plain.bind(traces, g.cmp_ptr, g.offset, g.dt, g.dx, wl["op"], wl["window"],
-                               wl["ap_lo"], wl["ap_hi"], store="f32")
-            comparison = compare_equal_accuracy(ctx, ctx_plain, bounds, dict(wl, name=args.workload),
-                                                store, g, wl["search_seed"])
+        if not args.no_compare and not args.no_gap and variants_for(args.workload, wl):
+            ctxs = {store: ctx}
+            for s in {v[1] for v in variants_for(args.workload, wl)} - {store}:
+                c = ens.Context(stream)
+                c.bind(traces, g.cmp_ptr, g.offset, g.dt, g.dx, wl["op"], wl["window"], wl["ap_lo"],
+                       wl["ap_hi"], store=s)
+                ctxs[s] = c
+            comparison = compare_equal_accuracy(ctxs, bounds, wl, g, wl["search_seed"], note)
 
     if wl["de"]["ens_enabled"]:
         expect = ens.evals_ens(P_d, de["np_lo"], de["ng_f"], de["np_bf"], de["ng_bf"],
@@ -301,23 +363,27 @@ def main():
     flops_per_launch = ex["sum_m"] * flops_per_pair(wl["op"], W) / ex["launches"]
     gbs = bytes_per_launch / per_launch_s / 1e9
     tflops = flops_per_launch / per_launch_s / 1e12
-    prof = measured_traffic(args.workload)
     kname = ("k_search_dense" if ex.get("dense") else "k_search") + \
-        f"<{wl['op']}, { {'f32': 0, 'f16': 1, 'bf16': 2}[store]}, {W}, 0>"
-    traffic = None
-    if prof is not None and prof["kernel"] == f"void ens::{kname}(ens::SearchArgs)":
-        traffic = round(prof["traffic_bytes_per_launch"])
+        f"<{wl['op']}, {DT_CODE[store]}, {W}, 0>"
+    shape = {"waves": ex.get("waves"), "item_order": ex.get("item_order"), "dense": ex.get("dense")}
+    prof = measured_profile(args.workload, f"void ens::{kname}(ens::SearchArgs)", shape)
+    traffic = None if prof is None else round(prof["traffic_bytes_per_launch"])
     roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": FP32_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": round(tflops / FP32_PEAK_TFLOPS, 4), "traffic": traffic,
             "flops_per_pair": flops_per_pair(wl["op"], W),
             "algorithmic_bytes_per_launch": round(bytes_per_launch),
-            "kernel": kname,
+            "kernel": kname, "shape": shape,
             "launches": ex["launches"], "avg_launch_ms": round(ex["device_ms"] / ex["launches"], 4),
-            "algorithmic_gather": {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                   "frac": round(gbs / HBM_PEAK_GBS, 4)},
-            # the same gathers against the per-CU vector-memory path they all pass through
+            # the same gathers against the per-CU vector-memory path every window
+            # load passes through (the second limit of the kernel)
             "vector_memory_path": {"achieved": round(gbs, 1), "peak": round(VMEM_PATH_PEAK_GBS, 1),
-                                   "unit": "GB/s", "frac": round(gbs / VMEM_PATH_PEAK_GBS, 4)}}
+                                   "unit": "GB/s", "frac": round(gbs / VMEM_PATH_PEAK_GBS, 4)},
+            # algorithmic gather bytes over time: served by L1/L2/MALL, not by
+            # HBM (the measured HBM bytes are "traffic"); not an HBM fraction
+            "cache_served_gather_gbs": round(gbs, 1)}
+    if prof is not None:
+        roof["measured"] = {k: prof[k] for k in ("hbm_gbs", "valu_busy", "ta_busy", "l2_hit",
+                                                 "profile") if k in prof}
 
     gap = None if args.no_gap else gap_stats(args.workload, S64, g.nt, g)
     line = {
@@ -327,15 +393,21 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": store, "data": "synthetic",
+        "dtype": "f32", "store": store,
+        "arithmetic": ("binary32 window interpolation and sums" if store != "f16" else
+                       "binary16 sample pairs times binary16 weights, exact products summed "
+                       "in binary32 (traveltimes on a 2^-11-sample grid); binary32 sums"),
+        "data": "synthetic",
         "config": {"workload": args.workload, "n_cmp": g.n_cmp, "offsets": int(g.cmp_ptr[1]),
-                   "nt": g.nt, "op": "CRS" if wl["op"] == 3 else "CMP", "window": W,
+                   "nt": g.nt, "dt": g.dt, "op": "CRS" if wl["op"] == 3 else "CMP", "window": W,
                    "aperture": [wl["ap_lo"], wl["ap_hi"]], "np": [de["np_lo"], de["np_hi"]],
                    "ng": de["ng_f"], "ens": bool(de["ens_enabled"]), "n_cycle": de["n_cycle"],
                    "n_bucket": de["n_bucket"], "polish_steps": de["polish_steps"],
-                   "zo_samples": P_d, "parallelism": "1 GPU"},
+                   "store": store, "zo_samples": P_d, "parallelism": "1 GPU"},
         "evals_per_s": round(evals * args.steps / sec, 1),
         "evals_per_step": evals,
+        "upload_ms": round(upload_ms, 2),
+        "bind_ms": round(bind_ms, 2),
         "gap": gap,
         "gap_ok": None if not gap or "mean" not in gap else bool(gap["mean"] <= 1e-3),
         "roofline": roof,
@@ -344,8 +416,8 @@ def main():
         "equal_accuracy": comparison,
     }
     if not args.no_cpu_baseline:
-        print("bench: CPU baseline (the oracle on a bounded sample)", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(g, wl, de, bounds)
+        note("CPU baseline (the oracle on a bounded sample, all cores then one core)")
+        line["cpu_baseline"] = cpu_baseline(g, wl, de, bounds, args.cpu_seconds)
     print(json.dumps(line), flush=True)
 
 

@@ -66,20 +66,35 @@ enum { ENS_MAX_POP = 64 };
 
 typedef struct ens_ctx ens_ctx;
 
-/* Trace samples, read once by ens_bind.  data: device, [n_traces][ld] binary32,
- * sample n of trace i at data[i*ld + n], time n*dt.  store_dtype chooses the
- * library's own storage: ENS_DTYPE_F32 keeps binary32; F16/BF16 keep
- * q_i[n] = round-to-nearest-even(binary32(u_i[n] / s_i)) with the per-trace
- * scale s_i = max_n |u_i[n]| (1 for an all-zero trace), plus a binary32 copy
- * for the binary64 re-scoring. */
+/* Trace samples, read once by ens_bind (#data of eq. Sf).  data: device
+ * [n_traces][ld], sample n of trace i at data[i*ld + n], time n*dt, of type
+ * data_dtype:
+ *  - ENS_DTYPE_F32: binary32 samples.  store_dtype chooses the library's
+ *    own storage: F32 keeps binary32; F16/BF16 keep q_i[n] =
+ *    round-to-nearest-even(u_i[n] / s_i) with the per-trace scale s_i the
+ *    smallest power of two at or above max_n |u_i[n]| (1 for an all-zero
+ *    trace; the quotient is exact), plus the binary32 samples for the
+ *    binary64 re-scoring and the stack.
+ *  - ENS_DTYPE_F16 / ENS_DTYPE_BF16: caller-quantised 16-bit samples
+ *    (binary16 / bfloat16 bit patterns) with scale (device [n_traces]) the
+ *    per-trace scales, each a positive power of two (ens_quantize writes
+ *    such scales; others are rejected with ENS_E_RANGE): the samples are
+ *    s_i q_i[n].  store_dtype must be data_dtype (searched in 16 bits) or F32
+ *    (the exact dequantised samples are stored).  master (optional, device
+ *    [n_traces][ld] binary32): the samples the binary64 re-scoring and the
+ *    stack read; NULL: the dequantised samples.
+ * scale and master are ignored for binary32 data.  Samples must be finite. */
 typedef struct {
     uint32_t struct_size;
-    const float *data;
+    const void *data;
     int64_t n_traces;
     int32_t nt;
     int64_t ld;
     float dt;
     int32_t store_dtype;
+    int32_t data_dtype;
+    const float *scale;
+    const float *master;
 } ens_traces;
 
 /* Acquisition geometry, host arrays.  Traces sorted by (CMP, offset);
@@ -249,15 +264,27 @@ ens_status ens_bind(ens_ctx *ctx, const ens_traces *traces, const ens_geometry *
 
 /* Per-trace scaled quantisation of [n_traces][ld] binary32 samples into
  * q: device [n_traces][nt] uint16 (binary16 or bfloat16 bits) and scale:
- * device [n_traces] (the same rule ens_bind applies). */
+ * device [n_traces], the smallest power of two at or above each trace's
+ * largest magnitude (the rule ens_bind applies; its output is valid 16-bit
+ * input for ens_bind). */
 ens_status ens_quantize(ens_ctx *ctx, const float *data, int64_t n_traces, int32_t nt, int64_t ld,
                         int32_t dtype, uint16_t *q, float *scale);
 
 /* ---- the search --------------------------------------------------------- */
 
-/* Search every sample of t0_grid (section "Traveltime parameter search":
- * maximise f(p) = S(p; #data, #config) within the box per sample). */
-ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *t0_grid, const ens_bounds *bounds,
+/* Search every sample of t0_grid over the bound data (section "Traveltime
+ * parameter search": maximise f(p) = S(p; #data, #config) within the box per
+ * sample). */
+ens_status ens_search_bound(ens_ctx *ctx, const ens_t0_grid *t0_grid, const ens_bounds *bounds,
+                            const ens_de_cfg *de_cfg, uint64_t seed, ens_result *out);
+
+/* The whole search in one call: ens_bind(traces, geometry, sem) followed by
+ * ens_search_bound(t0_grid, bounds, de_cfg, seed) — f(p) = S(p; #data,
+ * #config) maximised per sample, with #data = (traces, geometry) and #config =
+ * (sem, t0_grid) (eq. Sf).  Results and errors as for those two calls; the
+ * data stay bound to ctx afterwards. */
+ens_status ens_search(ens_ctx *ctx, const ens_traces *traces, const ens_geometry *geometry,
+                      const ens_sem_cfg *sem, const ens_t0_grid *t0_grid, const ens_bounds *bounds,
                       const ens_de_cfg *de_cfg, uint64_t seed, ens_result *out);
 
 /* ---- the objective and its adjoint --------------------------------------- */

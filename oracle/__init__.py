@@ -59,6 +59,7 @@ def lib():
         P = C.c_void_p
         L.or_philox4x64_10.argtypes = [P, P, P]
         L.or_num_threads.restype = C.c_int32
+        L.or_set_num_threads.argtypes = [C.c_int32]
         L.or_aperture.argtypes = [C.POINTER(_Line), C.c_int32]
         L.or_aperture.restype = C.c_int32
         L.or_pop_size.argtypes = [C.POINTER(_DeCfg), C.c_int32, C.c_int32]
@@ -66,6 +67,7 @@ def lib():
         L.or_sample_bounds.argtypes = [C.POINTER(_Line), C.POINTER(_Bounds), C.c_int32, P, P]
         L.or_semblance_batch.argtypes = [C.POINTER(_Line), C.c_int64, P, P, P, P, P, P]
         L.or_semblance_grad_batch.argtypes = [C.POINTER(_Line), C.c_int64, P, P, P, P, P]
+        L.or_semblance_tau_l1_batch.argtypes = [C.POINTER(_Line), C.c_int64, P, P, P, P]
         L.or_de_trial.argtypes = [C.c_int32, C.c_int32, P, P, P, C.c_float, C.c_float, P, P, P]
         L.or_search.argtypes = [C.POINTER(_Line), C.POINTER(_Bounds), C.POINTER(_DeCfg),
                                 C.c_uint64, P, C.c_int32, C.c_int32, C.c_int32, P, P]
@@ -172,6 +174,16 @@ class Line:
         lib().or_semblance_grad_batch(C.byref(self._s), n, _ptr(cmp), _ptr(t), _ptr(p), _ptr(S),
                                       _ptr(g))
         return S, g
+
+    def tau_sensitivity(self, cmp, t, params):
+        """Sum over participating traces of |dS/dtau_i| (tau in samples) per candidate."""
+        cmp = np.ascontiguousarray(cmp, dtype=np.int32)
+        t = np.ascontiguousarray(t, dtype=np.int32)
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(-1, self.op))
+        out = np.zeros(cmp.size)
+        lib().or_semblance_tau_l1_batch(C.byref(self._s), cmp.size, _ptr(cmp), _ptr(t), _ptr(p),
+                                        _ptr(out))
+        return out
 
     def search(self, bounds, de, seed, cmp_out=None, t_begin=0, t_end=None, objective=0,
                inject=1):

@@ -56,8 +56,9 @@ typedef struct {
     int32_t adapt;          /* 1: JADE control-parameter adaptation and archive (F, CR: initial means) */
 } or_de_cfg;
 
-/* OpenMP threads the oracle's parallel loops use. */
+/* OpenMP threads the oracle's parallel loops use, and setting them. */
 int32_t or_num_threads(void);
+void or_set_num_threads(int32_t n);
 
 /* counter-based generator: Philox-4x64 with 10 rounds (Salmon et al., SC'11) */
 void or_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
@@ -73,6 +74,12 @@ double or_semblance(const or_line *L, int32_t j, int32_t n0, const double *p,
                     int32_t *M_out, double *margin_out);
 void or_semblance_batch(const or_line *L, int64_t n, const int32_t *cmp, const int32_t *t,
                         const double *params, double *S, int32_t *M, double *margin);
+/* Sensitivity of S to the traveltimes: sum over the participating traces of
+ * |dS/dtau_i| (tau in samples, M held fixed, right derivative at integer
+ * traveltime).  A traveltime error of at most delta samples per trace moves S
+ * by at most about delta times this sum (first order). */
+void or_semblance_tau_l1_batch(const or_line *L, int64_t n, const int32_t *cmp, const int32_t *t,
+                               const double *params, double *l1);
 /* Gradient dS/dp (M held fixed, right derivative at integer traveltime). */
 double or_semblance_grad(const or_line *L, int32_t j, int32_t n0, const double *p, double *g);
 void or_semblance_grad_batch(const or_line *L, int64_t n, const int32_t *cmp, const int32_t *t,
@@ -130,8 +137,9 @@ void or_polish(const or_line *L, const or_bounds *B, int64_t n, const int32_t *c
                const int32_t *t, const float *p_in, double lr, int32_t steps,
                double *p_out, double *S_out);
 
-/* Per-trace scaled reduced-precision storage: scale = max|u| (1 if the trace
- * is all zero), q = round-to-nearest-even(binary32(u / scale)). */
+/* Per-trace scaled reduced-precision storage: scale = the smallest power of
+ * two at or above max|u| (1 if the trace is all zero), q =
+ * round-to-nearest-even(u / scale) (the quotient is exact in binary32). */
 void or_quantize(const float *u, int64_t n_tr, int32_t nt, int32_t dtype /*1 f16, 2 bf16*/,
                  uint16_t *q, float *scale);
 double or_half_to_double(uint16_t h);

@@ -3,8 +3,12 @@
  * from the IEEE 754 binary16 format and the bfloat16 format (binary32 with
  * the low 16 mantissa bits dropped).  Test infrastructure (see oracle.h).
  *
- * scale_i = max_n |u_i[n]| (1 when the trace is all zero);
- * q_i[n] = round-to-nearest-even(binary32 quotient u_i[n] / scale_i).
+ * scale_i = the smallest power of two at or above max_n |u_i[n]| (1 when the
+ * trace is all zero); q_i[n] = round-to-nearest-even(u_i[n] / scale_i), the
+ * quotient exact in binary32.  A power-of-two scale leaves the relative
+ * precision of the floating-point formats unchanged and makes s_i q_i[n]
+ * exact, so the scale can be applied to interpolation weights without
+ * rounding.
  */
 #include <math.h>
 #include <string.h>
@@ -87,8 +91,13 @@ void or_quantize(const float *u, int64_t n_tr, int32_t nt, int32_t dtype, uint16
         for (int32_t n = 0; n < nt; ++n)
             if (fabsf(row[n]) > s)
                 s = fabsf(row[n]);
-        if (s == 0.0f)
+        if (s == 0.0f) {
             s = 1.0f;
+        } else {
+            int e = 0;
+            const float fr = frexpf(s, &e); /* s = fr 2^e, fr in [1/2, 1) */
+            s = fr == 0.5f ? s : ldexpf(1.0f, e);
+        }
         scale[i] = s;
         for (int32_t n = 0; n < nt; ++n) {
             float x = row[n] / s;

@@ -91,6 +91,16 @@ int32_t or_num_threads(void)
 #endif
 }
 
+void or_set_num_threads(int32_t n)
+{
+#ifdef _OPENMP
+    if (n > 0)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int32_t or_pop_size(const or_de_cfg *cfg, int32_t nt, int32_t n0)
 {
     if (nt <= 1)

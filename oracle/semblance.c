@@ -64,7 +64,7 @@ static double traveltime_sq(const or_line *L, const double *p, double t0, double
 /* Shared walk over the aperture: fills the window sums, and optionally the
  * gradient in a second pass once S is known. */
 static double semblance_impl(const or_line *L, int32_t j, int32_t n0, const double *p,
-                             int32_t *M_out, double *margin_out, double *grad)
+                             int32_t *M_out, double *margin_out, double *grad, double *tau_l1)
 {
     const int w = L->half_w, W = 2 * w + 1;
     const int P = L->op;
@@ -105,6 +105,8 @@ static double semblance_impl(const or_line *L, int32_t j, int32_t n0, const doub
         N += s[k] * s[k];
     double S = (M > 0 && E > 0.0) ? N / ((double)M * E) : 0.0;
 
+    if (tau_l1)
+        *tau_l1 = 0.0;
     if (grad) {
         for (int d = 0; d < P; ++d)
             grad[d] = 0.0;
@@ -131,6 +133,8 @@ static double semblance_impl(const or_line *L, int32_t j, int32_t n0, const doub
                     }
                     for (int d = 0; d < P; ++d)
                         grad[d] += dS_dtau * dq[d] / (2.0 * t * L->dt);
+                    if (tau_l1)
+                        *tau_l1 += fabs(dS_dtau);
                 }
             }
         }
@@ -146,12 +150,12 @@ static double semblance_impl(const or_line *L, int32_t j, int32_t n0, const doub
 double or_semblance(const or_line *L, int32_t j, int32_t n0, const double *p, int32_t *M_out,
                     double *margin_out)
 {
-    return semblance_impl(L, j, n0, p, M_out, margin_out, NULL);
+    return semblance_impl(L, j, n0, p, M_out, margin_out, NULL, NULL);
 }
 
 double or_semblance_grad(const or_line *L, int32_t j, int32_t n0, const double *p, double *g)
 {
-    return semblance_impl(L, j, n0, p, NULL, NULL, g);
+    return semblance_impl(L, j, n0, p, NULL, NULL, g, NULL);
 }
 
 void or_semblance_batch(const or_line *L, int64_t n, const int32_t *cmp, const int32_t *t,
@@ -177,4 +181,15 @@ void or_semblance_grad_batch(const or_line *L, int64_t n, const int32_t *cmp, co
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t c = 0; c < n; ++c)
         S[c] = or_semblance_grad(L, cmp[c], t[c], params + c * P, grad + c * P);
+}
+
+void or_semblance_tau_l1_batch(const or_line *L, int64_t n, const int32_t *cmp, const int32_t *t,
+                               const double *params, double *l1)
+{
+    const int P = L->op;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t c = 0; c < n; ++c) {
+        double g[3];
+        semblance_impl(L, cmp[c], t[c], params + c * P, NULL, NULL, g, l1 + c);
+    }
 }

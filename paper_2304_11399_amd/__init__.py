@@ -35,7 +35,8 @@ class EnsError(RuntimeError):
 # ----------------------------------------------------------------- structs
 class Traces(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("data", C.c_void_p), ("n_traces", C.c_int64),
-                ("nt", C.c_int32), ("ld", C.c_int64), ("dt", C.c_float), ("store_dtype", C.c_int32)]
+                ("nt", C.c_int32), ("ld", C.c_int64), ("dt", C.c_float), ("store_dtype", C.c_int32),
+                ("data_dtype", C.c_int32), ("scale", C.c_void_p), ("master", C.c_void_p)]
 
 
 class Geometry(C.Structure):
@@ -115,8 +116,11 @@ _SIGS = {
     "ens_last_stats": (C.c_int, [_P, C.POINTER(Stats)]),
     "ens_bind": (C.c_int, [_P, C.POINTER(Traces), C.POINTER(Geometry), C.POINTER(SemCfg)]),
     "ens_quantize": (C.c_int, [_P, _P, C.c_int64, C.c_int32, C.c_int64, C.c_int32, _P, _P]),
-    "ens_search": (C.c_int, [_P, C.POINTER(T0Grid), C.POINTER(Bounds), C.POINTER(DeCfg),
-                             C.c_uint64, C.POINTER(Result)]),
+    "ens_search_bound": (C.c_int, [_P, C.POINTER(T0Grid), C.POINTER(Bounds), C.POINTER(DeCfg),
+                                   C.c_uint64, C.POINTER(Result)]),
+    "ens_search": (C.c_int, [_P, C.POINTER(Traces), C.POINTER(Geometry), C.POINTER(SemCfg),
+                             C.POINTER(T0Grid), C.POINTER(Bounds), C.POINTER(DeCfg), C.c_uint64,
+                             C.POINTER(Result)]),
     "ens_stack": (C.c_int, [_P, C.POINTER(T0Grid), _P, _P, _P, C.POINTER(C.c_double)]),
     "ens_jade_draws": (C.c_int, [_P, C.c_int64, _P, C.c_double, C.c_double, C.c_int32, _P, _P, _P]),
     "semblance_eval": (C.c_int, [_P, C.POINTER(Candidates), _P, _P]),
@@ -212,24 +216,55 @@ class Context:
         return d
 
     # -------------------------------------------------------------- data
-    def bind(self, traces, cmp_ptr, offset, dt, dx, op, window, ap_lo=0, ap_hi=None,
-             store="f32"):
-        """traces: device float32 [n_traces, nt] (row stride taken from the tensor)."""
+    def _data_structs(self, traces, cmp_ptr, offset, dt, dx, op, window, ap_lo, ap_hi, store, scale,
+                      master, data_dtype):
         import torch
-        _require_cuda(traces)
-        assert traces.dtype == torch.float32 and traces.dim() == 2 and traces.stride(1) == 1
+        _require_cuda(traces, scale, master)
+        assert traces.dim() == 2 and traces.stride(1) == 1
+        if traces.dtype == torch.float32:
+            data_dtype = "f32"
+        elif traces.dtype == torch.float16:
+            data_dtype = "f16"
+        elif traces.dtype == torch.bfloat16:
+            data_dtype = "bf16"
+        else:
+            assert traces.dtype in (torch.int16, torch.uint16) and data_dtype in ("f16", "bf16"), \
+                "16-bit bit patterns need data_dtype 'f16' or 'bf16'"
+        if data_dtype != "f32":
+            assert scale is not None and scale.dtype == torch.float32 and scale.is_contiguous()
+            assert scale.numel() == traces.shape[0]
+            if master is not None:
+                assert master.dtype == torch.float32 and master.stride() == traces.stride()
+            store = data_dtype if store is None else store
+        store = "f32" if store is None else store
         cmp_ptr = np.ascontiguousarray(cmp_ptr, dtype=np.int64)
         offset = np.ascontiguousarray(offset, dtype=np.float32)
         tr = _sized(Traces, data=traces.data_ptr(), n_traces=traces.shape[0], nt=traces.shape[1],
-                    ld=traces.stride(0), dt=float(dt), store_dtype=DTYPES[store])
+                    ld=traces.stride(0), dt=float(dt), store_dtype=DTYPES[store],
+                    data_dtype=DTYPES[data_dtype], scale=None if scale is None else scale.data_ptr(),
+                    master=None if master is None else master.data_ptr())
         geo = _sized(Geometry, cmp_ptr=cmp_ptr.ctypes.data, n_cmp=cmp_ptr.size - 1, dx=float(dx),
                      offset=offset.ctypes.data)
         sem = _sized(SemCfg, op=OPS[op], window=int(window), ap_lo=int(ap_lo),
                      ap_hi=int(ap_lo if ap_hi is None else ap_hi))
-        self._check(self._lib.ens_bind(self._h, C.byref(tr), C.byref(geo), C.byref(sem)))
+        return tr, geo, sem, (cmp_ptr, offset)
+
+    def _bound_as(self, traces, cmp_ptr, op):
         self.nparam = OPS[op]
         self.nt = traces.shape[1]
-        self.n_cmp = cmp_ptr.size - 1
+        self.n_cmp = np.asarray(cmp_ptr).size - 1
+
+    def bind(self, traces, cmp_ptr, offset, dt, dx, op, window, ap_lo=0, ap_hi=None,
+             store=None, scale=None, master=None, data_dtype=None):
+        """traces: device [n_traces, nt] (row stride taken from the tensor): float32
+        samples, or 16-bit samples (float16 / bfloat16, or int16 bit patterns with
+        data_dtype 'f16'/'bf16') with per-trace power-of-two scales and an
+        optional float32 master.  store: the library's storage ('f32', 'f16',
+        'bf16'; default: binary32 for binary32 data, else the data's type)."""
+        tr, geo, sem, keep = self._data_structs(traces, cmp_ptr, offset, dt, dx, op, window, ap_lo,
+                                                ap_hi, store, scale, master, data_dtype)
+        self._check(self._lib.ens_bind(self._h, C.byref(tr), C.byref(geo), C.byref(sem)))
+        self._bound_as(traces, cmp_ptr, op)
 
     def quantize(self, data, dtype):
         import torch
@@ -242,19 +277,19 @@ class Context:
         return q, s
 
     # -------------------------------------------------------------- search
-    def search(self, bounds, de, seed, cmp_out=None, t_begin=0, t_end=None, rescore_fp64=True,
-               keep_pre_polish=False):
-        """Run the search; returns a dict of device tensors and host counters."""
+    def _search_structs(self, P, nt, n_cmp, bounds, de, cmp_out, t_begin, t_end, rescore_fp64,
+                        keep_pre_polish):
         import torch
-        P = self.nparam
-        t_end = self.nt if t_end is None else int(t_end)
-        n_out = self.n_cmp if cmp_out is None else len(cmp_out)
+        t_end = nt if t_end is None else int(t_end)
+        n_out = n_cmp if cmp_out is None else len(cmp_out)
         n_t = t_end - t_begin
         dev = torch.device("cuda", torch.cuda.current_device())
-        params = torch.empty((n_out, n_t, P), dtype=torch.float32, device=dev)
-        S = torch.empty((n_out, n_t), dtype=torch.float32, device=dev)
-        S64 = torch.empty((n_out, n_t), dtype=torch.float64, device=dev) if rescore_fp64 else None
-        S_pre = torch.empty((n_out, n_t), dtype=torch.float32, device=dev) if keep_pre_polish else None
+        outs = dict(params=torch.empty((n_out, n_t, P), dtype=torch.float32, device=dev),
+                    S=torch.empty((n_out, n_t), dtype=torch.float32, device=dev),
+                    S64=torch.empty((n_out, n_t), dtype=torch.float64, device=dev)
+                    if rescore_fp64 else None,
+                    S_pre_polish=torch.empty((n_out, n_t), dtype=torch.float32, device=dev)
+                    if keep_pre_polish else None)
         co = None if cmp_out is None else np.ascontiguousarray(cmp_out, dtype=np.int32)
         grid = _sized(T0Grid, cmp_out=None if co is None else co.ctypes.data, n_cmp_out=n_out,
                       t_begin=int(t_begin), t_end=t_end)
@@ -264,13 +299,40 @@ class Context:
             b.lo[d] = float(lo[d]) if d < len(lo) else 0.0
             b.hi[d] = float(hi[d]) if d < len(hi) else 0.0
         cfg = de_cfg(de, rescore_fp64=rescore_fp64)
-        res = _sized(Result, params=params.data_ptr(), S=S.data_ptr(),
-                     S64=None if S64 is None else S64.data_ptr(),
-                     S_pre_polish=None if S_pre is None else S_pre.data_ptr())
-        self._check(self._lib.ens_search(self._h, C.byref(grid), C.byref(b), C.byref(cfg),
+        res = _sized(Result, params=outs["params"].data_ptr(), S=outs["S"].data_ptr(),
+                     S64=None if outs["S64"] is None else outs["S64"].data_ptr(),
+                     S_pre_polish=None if outs["S_pre_polish"] is None
+                     else outs["S_pre_polish"].data_ptr())
+        return grid, b, cfg, res, outs, co
+
+    def search(self, bounds, de, seed, cmp_out=None, t_begin=0, t_end=None, rescore_fp64=True,
+               keep_pre_polish=False):
+        """Search the bound data (ens_search_bound); returns a dict of device
+        tensors and host counters."""
+        grid, b, cfg, res, outs, keep = self._search_structs(
+            self.nparam, self.nt, self.n_cmp, bounds, de, cmp_out, t_begin, t_end, rescore_fp64,
+            keep_pre_polish)
+        self._check(self._lib.ens_search_bound(self._h, C.byref(grid), C.byref(b), C.byref(cfg),
+                                               C.c_uint64(int(seed)), C.byref(res)))
+        return dict(outs, n_evals=int(res.n_evals), sum_m=int(res.sum_m))
+
+    def search_traces(self, traces, geometry, sem, bounds, de, seed, cmp_out=None, t_begin=0,
+                      t_end=None, rescore_fp64=True, keep_pre_polish=False, store=None, scale=None,
+                      master=None, data_dtype=None):
+        """The one-call search (ens_search): bind (traces, geometry, sem) and
+        search.  geometry = (cmp_ptr, offset, dt, dx); sem = (op, window, ap_lo, ap_hi)."""
+        cmp_ptr, offset, dt, dx = geometry
+        op, window, ap_lo, ap_hi = sem
+        tr, geo, sc, keep = self._data_structs(traces, cmp_ptr, offset, dt, dx, op, window, ap_lo,
+                                               ap_hi, store, scale, master, data_dtype)
+        grid, b, cfg, res, outs, keep2 = self._search_structs(
+            OPS[op], traces.shape[1], np.asarray(cmp_ptr).size - 1, bounds, de, cmp_out, t_begin,
+            t_end, rescore_fp64, keep_pre_polish)
+        self._check(self._lib.ens_search(self._h, C.byref(tr), C.byref(geo), C.byref(sc),
+                                         C.byref(grid), C.byref(b), C.byref(cfg),
                                          C.c_uint64(int(seed)), C.byref(res)))
-        return dict(params=params, S=S, S64=S64, S_pre_polish=S_pre, n_evals=int(res.n_evals),
-                    sum_m=int(res.sum_m))
+        self._bound_as(traces, cmp_ptr, op)
+        return dict(outs, n_evals=int(res.n_evals), sum_m=int(res.sum_m))
 
     def stack(self, params, S=None, cmp_out=None, t_begin=0, t_end=None):
         """Zero-offset stack along each sample's operator (device [n_out, n_t]),
@@ -370,16 +432,17 @@ def de_cfg(de, rescore_fp64=True):
 
 
 def ens_search(traces, geometry, t0_grid, bounds, de_cfg_, seed, *, op, window, ap_lo=0,
-               ap_hi=None, store="f32", ctx=None):
-    """One-call search: bind (traces, geometry) and search the t0 grid.
+               ap_hi=None, store=None, scale=None, master=None, data_dtype=None, ctx=None):
+    """One-call search through the C entry point ens_search: bind (traces,
+    geometry) and search the t0 grid.
 
     geometry = (cmp_ptr, offset, dt, dx); t0_grid = (cmp_out or None, t_begin, t_end).
     """
     ctx = ctx or Context()
-    cmp_ptr, offset, dt, dx = geometry
-    ctx.bind(traces, cmp_ptr, offset, dt, dx, op, window, ap_lo, ap_hi, store)
     cmp_out, t_begin, t_end = t0_grid
-    return ctx.search(bounds, de_cfg_, seed, cmp_out, t_begin, t_end)
+    return ctx.search_traces(traces, geometry, (op, window, ap_lo, ap_hi), bounds, de_cfg_, seed,
+                             cmp_out, t_begin, t_end, store=store, scale=scale, master=master,
+                             data_dtype=data_dtype)
 
 
 def _semblance_fn():

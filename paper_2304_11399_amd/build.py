@@ -9,7 +9,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libens.so")
-SOURCES = ["api.cpp", "kernels.hip"]
+SOURCES = ["api.cpp", "kernels.hip", "search_f32.hip", "search_f16.hip", "search_bf16.hip"]
 ARCH = "gfx950"
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

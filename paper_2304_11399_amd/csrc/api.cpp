@@ -2,12 +2,17 @@
 // (plain per-sample evolution or ENS sweeps) and the objective entry points.
 #include <hip/hip_runtime.h>
 
+#include <dlfcn.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <map>
+#include <mutex>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -59,7 +64,10 @@ struct ens_ctx {
     int32_t nt = 0, n_cmp = 0, store_dtype = ENS_DTYPE_F32;
     float dt = 0.f, dx = 0.f;
     int32_t op = 0, window = 0, ap_lo = 0, ap_hi = 0;
-    DevBuf store, master, scale, meta, cmp_ptr, ap_tab;
+    DevBuf store, master, scale, meta, cmp_ptr, ap_tab, qexp, wsc16;
+    // binary16 window constants (StoreView h16_*)
+    float h16_kq = 0.f;
+    uint32_t h16_bbits = 0, h16_shift = 0;
     // search workspace
     DevBuf lo_tab, hi_tab, items, X, XS, Y, YS, counters, cmp_out, flag, progress;
     // statistics of the last search, launch timing events
@@ -80,6 +88,7 @@ struct ens_ctx {
         int nsl, order, dense;
     };
     std::map<std::string, Shape> tune_cache;
+    std::string device_tag;   // "<arch>/<CUs>": prefix of the keys in the shape file
     hipGraphExec_t graph_exec = nullptr;
     hipGraph_t graph = nullptr;
     void drop_graph()
@@ -94,7 +103,7 @@ struct ens_ctx {
     {
         drop_graph();
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
-        for (DevBuf *b : {&store, &master, &scale, &meta, &cmp_ptr, &ap_tab, &lo_tab, &hi_tab, &items,
+        for (DevBuf *b : {&store, &master, &scale, &meta, &cmp_ptr, &ap_tab, &qexp, &wsc16, &lo_tab, &hi_tab, &items,
                           &X, &XS, &Y, &YS, &counters, &cmp_out, &flag, &progress})
             b->release();
     }
@@ -161,13 +170,74 @@ ens::StoreView view_of(const ens_ctx *c, bool master)
     v.dt = c->dt;
     v.dx = c->dx;
     v.ap_tab = c->ap_tab.as<int32_t>();
+    v.wsc16 = half ? c->wsc16.as<uint32_t>() : nullptr;
+    v.h16_kq = c->h16_kq;
+    v.h16_bbits = c->h16_bbits;
+    v.h16_shift = c->h16_shift;
+    v.tau_max = static_cast<float>(c->nt - 1);
     return v;
+}
+
+bool is_pow2(float x)
+{
+    if (!(x > 0.f) || !std::isfinite(x)) return false;
+    int e = 0;
+    return std::frexp(x, &e) == 0.5f;
 }
 
 bool finite(float x) { return std::isfinite(x); }
 
 // Device-side range check of candidate indices (they live in device memory).
 ens_status check_candidates(ens_ctx *ctx, const ens_candidates *cands);
+
+// Measured launch shapes persist in a text file shared by the processes that
+// load the library: one line "<device>/<key> <slices> <item order> <dense>"
+// per shape.  The file is ENS_TUNE_CACHE if that is set ("off": none), else
+// ens_tune_cache.txt beside the library.  Lines are appended as shapes are
+// measured; a later line for the same key wins.  Unreadable or unwritable
+// files are ignored: the shapes are then measured again.
+std::mutex tune_file_mutex;
+
+std::string tune_file_path()
+{
+    const char *env = std::getenv("ENS_TUNE_CACHE");
+    if (env) return std::string(env) == "off" ? std::string() : std::string(env);
+    Dl_info info{};
+    if (!dladdr(reinterpret_cast<void *>(&ens_version), &info) || !info.dli_fname) return std::string();
+    std::string lib(info.dli_fname);
+    const size_t slash = lib.rfind('/');
+    return (slash == std::string::npos ? std::string(".") : lib.substr(0, slash)) + "/ens_tune_cache.txt";
+}
+
+void load_tune_file(ens_ctx *ctx)
+{
+    const std::string path = tune_file_path();
+    if (path.empty()) return;
+    std::lock_guard<std::mutex> lock(tune_file_mutex);
+    std::ifstream in(path);
+    std::string line;
+    const std::string prefix = ctx->device_tag + "/";
+    while (std::getline(in, line)) {
+        std::istringstream ls(line);
+        std::string key;
+        ens_ctx::Shape sh{};
+        if (!(ls >> key >> sh.nsl >> sh.order >> sh.dense)) continue;
+        if (key.compare(0, prefix.size(), prefix) != 0) continue;
+        if (!(sh.nsl == 1 || sh.nsl == 2 || sh.nsl == 4 || sh.nsl == 8) || sh.order < 1 || sh.order > 3 ||
+            sh.dense < 0 || sh.dense > 1)
+            continue;
+        ctx->tune_cache[key.substr(prefix.size())] = sh;
+    }
+}
+
+void save_tune_entry(const ens_ctx *ctx, const std::string &key, const ens_ctx::Shape &sh)
+{
+    const std::string path = tune_file_path();
+    if (path.empty()) return;
+    std::lock_guard<std::mutex> lock(tune_file_mutex);
+    std::ofstream out(path, std::ios::app);
+    if (out) out << ctx->device_tag << "/" << key << " " << sh.nsl << " " << sh.order << " " << sh.dense << "\n";
+}
 
 }  // namespace
 
@@ -185,6 +255,14 @@ ens_status ens_ctx_create(ens_ctx **out, void *stream)
     if (!c) return ENS_E_OOM;
     c->stream = static_cast<hipStream_t>(stream);
     c->tuning.struct_size = sizeof(ens_tuning);
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        std::string arch(prop.gcnArchName);
+        arch = arch.substr(0, arch.find(':'));
+        c->device_tag = arch + "/" + std::to_string(prop.multiProcessorCount);
+        load_tune_file(c);
+    }
     *out = c;
     return ENS_OK;
 }
@@ -236,6 +314,12 @@ ens_status ens_bind(ens_ctx *ctx, const ens_traces *tr, const ens_geometry *g, c
         return fail(ctx, ENS_E_RANGE, "ens_bind: dt and dx must be positive");
     if (tr->store_dtype < ENS_DTYPE_F32 || tr->store_dtype > ENS_DTYPE_BF16)
         return fail(ctx, ENS_E_INVALID, "ens_bind: unknown store dtype %d", tr->store_dtype);
+    if (tr->data_dtype < ENS_DTYPE_F32 || tr->data_dtype > ENS_DTYPE_BF16)
+        return fail(ctx, ENS_E_INVALID, "ens_bind: unknown data dtype %d", tr->data_dtype);
+    const bool data16 = tr->data_dtype != ENS_DTYPE_F32;
+    if (data16 && tr->store_dtype != ENS_DTYPE_F32 && tr->store_dtype != tr->data_dtype)
+        return fail(ctx, ENS_E_UNSUPPORTED, "ens_bind: 16-bit data are stored as they are or as binary32");
+    if (data16 && !tr->scale) return fail(ctx, ENS_E_INVALID, "ens_bind: 16-bit data need per-trace scales");
     if (g->n_cmp < 1) return fail(ctx, ENS_E_INVALID, "ens_bind: n_cmp < 1");
     if (g->cmp_ptr[0] != 0 || g->cmp_ptr[g->n_cmp] != tr->n_traces)
         return fail(ctx, ENS_E_INVALID, "ens_bind: cmp_ptr must start at 0 and end at n_traces");
@@ -248,23 +332,68 @@ ens_status ens_bind(ens_ctx *ctx, const ens_traces *tr, const ens_geometry *g, c
         return fail(ctx, ENS_E_RANGE, "ens_bind: window must be odd, 3..%d (got %d)", 2 * ENS_MAX_HALF_WINDOW + 1,
                     sem->window);
     if (sem->ap_lo < 0 || sem->ap_hi < 0) return fail(ctx, ENS_E_RANGE, "ens_bind: negative aperture");
+    if (data16) {
+        // the scales fold into binary16 interpolation weights exactly only as powers of two
+        std::vector<float> sc(static_cast<size_t>(tr->n_traces));
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(sc.data(), tr->scale, sc.size() * sizeof(float), hipMemcpyDeviceToHost,
+                                        ctx->stream));
+        HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+        for (size_t i = 0; i < sc.size(); ++i)
+            if (!is_pow2(sc[i]))
+                return fail(ctx, ENS_E_RANGE, "ens_bind: scale[%zu] = %g is not a positive power of two", i,
+                            static_cast<double>(sc[i]));
+    }
 
     const int64_t n_tr = tr->n_traces;
     const int32_t nt = tr->nt;
     const int64_t ld = ((nt + 2 * PAD) + 63) / 64 * 64;
     ctx->bound = false;
+    const bool store16 = tr->store_dtype != ENS_DTYPE_F32;
     // 16-bit rows hold two copies, the second shifted by one sample, so that
     // every window starts on a dword boundary in one of them
-    const size_t row_bytes = tr->store_dtype == ENS_DTYPE_F32 ? 4 * ld : 2 * 2 * ld;
+    const size_t row_bytes = store16 ? 2 * 2 * ld : 4 * ld;
     HIP_OR_FAIL(ctx, ctx->store.ensure(static_cast<size_t>(n_tr) * row_bytes));
     HIP_OR_FAIL(ctx, ctx->scale.ensure(static_cast<size_t>(n_tr) * sizeof(float)));
-    if (tr->store_dtype == ENS_DTYPE_F32) {
-        HIP_OR_FAIL(ctx, ens::launch_store_f32(tr->data, tr->ld, n_tr, nt, ld, ctx->store.as<float>(), ctx->stream));
-    } else {
+    HIP_OR_FAIL(ctx, ctx->qexp.ensure(static_cast<size_t>(n_tr) * sizeof(int32_t)));
+    HIP_OR_FAIL(ctx, ctx->wsc16.ensure(static_cast<size_t>(n_tr) * sizeof(uint32_t)));
+    if (!data16 && !store16) {
+        HIP_OR_FAIL(ctx, ens::launch_store_f32(static_cast<const float *>(tr->data), tr->ld, n_tr, nt, ld,
+                                               ctx->store.as<float>(), ctx->stream));
+    } else if (!data16) {
         HIP_OR_FAIL(ctx, ctx->master.ensure(static_cast<size_t>(n_tr) * ld * 4));
-        HIP_OR_FAIL(ctx, ens::launch_store_f32(tr->data, tr->ld, n_tr, nt, ld, ctx->master.as<float>(), ctx->stream));
-        HIP_OR_FAIL(ctx, ens::launch_quantize(tr->data, tr->ld, n_tr, nt, tr->store_dtype, ctx->store.as<uint16_t>(),
-                                              ld, PAD, ctx->scale.as<float>(), true, ctx->stream));
+        HIP_OR_FAIL(ctx, ens::launch_store_f32(static_cast<const float *>(tr->data), tr->ld, n_tr, nt, ld,
+                                               ctx->master.as<float>(), ctx->stream));
+        HIP_OR_FAIL(ctx, ens::launch_quantize(static_cast<const float *>(tr->data), tr->ld, n_tr, nt, tr->store_dtype,
+                                              ctx->store.as<uint16_t>(), ld, PAD, ctx->scale.as<float>(), true,
+                                              ctx->qexp.as<int32_t>(), ctx->stream));
+    } else {
+        // caller-quantised rows: the dual 16-bit layout when searched in 16 bits, the binary32
+        // samples from master or dequantised
+        float *f32_rows = nullptr;
+        if (store16) {
+            HIP_OR_FAIL(ctx, ctx->master.ensure(static_cast<size_t>(n_tr) * ld * 4));
+            f32_rows = ctx->master.as<float>();
+        } else {
+            f32_rows = ctx->store.as<float>();
+        }
+        uint16_t *rows16 = store16 ? ctx->store.as<uint16_t>() : nullptr;
+        HIP_OR_FAIL(ctx, ens::launch_store16(static_cast<const uint16_t *>(tr->data), tr->ld, n_tr, nt,
+                                             tr->data_dtype, tr->scale, rows16, ld,
+                                             tr->master ? nullptr : f32_rows, ctx->qexp.as<int32_t>(), ctx->stream));
+        if (tr->master)
+            HIP_OR_FAIL(ctx, ens::launch_store_f32(tr->master, tr->ld, n_tr, nt, ld, f32_rows, ctx->stream));
+    }
+    if (store16)
+        HIP_OR_FAIL(ctx, ens::launch_relscale(ctx->qexp.as<int32_t>(), n_tr, ctx->scale.as<float>(),
+                                              ctx->wsc16.as<uint32_t>(), ctx->stream));
+    {
+        // binary16 window grid: B = the smallest power of two >= max(4096, nt + PAD)
+        int lb = 12;
+        while ((int64_t(1) << lb) < static_cast<int64_t>(nt) + PAD) ++lb;
+        const float B = std::ldexp(1.0f, lb);
+        ctx->h16_kq = B + static_cast<float>(PAD - sem->window / 2);
+        std::memcpy(&ctx->h16_bbits, &B, sizeof B);
+        ctx->h16_shift = static_cast<uint32_t>(22 - lb);
     }
     std::vector<TraceMeta> meta(static_cast<size_t>(n_tr));
     for (int32_t c = 0; c < g->n_cmp; ++c)
@@ -311,16 +440,28 @@ ens_status ens_quantize(ens_ctx *ctx, const float *data, int64_t n_traces, int32
     if (n_traces < 0 || nt < 1 || ld < nt) return fail(ctx, ENS_E_INVALID, "ens_quantize: bad sizes");
     if (dtype != ENS_DTYPE_F16 && dtype != ENS_DTYPE_BF16)
         return fail(ctx, ENS_E_INVALID, "ens_quantize: dtype must be F16 or BF16");
-    HIP_OR_FAIL(ctx, ens::launch_quantize(data, ld, n_traces, nt, dtype, q, nt, 0, scale, false, ctx->stream));
+    HIP_OR_FAIL(ctx, ens::launch_quantize(data, ld, n_traces, nt, dtype, q, nt, 0, scale, false, nullptr,
+                                          ctx->stream));
     ctx->err.clear();
     return ENS_OK;
 }
 
-ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *bounds,
+ens_status ens_search(ens_ctx *ctx, const ens_traces *traces, const ens_geometry *geometry,
+                      const ens_sem_cfg *sem, const ens_t0_grid *grid, const ens_bounds *bounds,
                       const ens_de_cfg *de, uint64_t seed, ens_result *out)
 {
     if (!ctx) return ENS_E_INVALID;
-    if (!ctx->bound) return fail(ctx, ENS_E_STATE, "ens_search: call ens_bind first");
+    if (!grid || !bounds || !de || !out) return fail(ctx, ENS_E_INVALID, "ens_search: null argument");
+    const ens_status st = ens_bind(ctx, traces, geometry, sem);
+    if (st != ENS_OK) return st;
+    return ens_search_bound(ctx, grid, bounds, de, seed, out);
+}
+
+ens_status ens_search_bound(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *bounds,
+                            const ens_de_cfg *de, uint64_t seed, ens_result *out)
+{
+    if (!ctx) return ENS_E_INVALID;
+    if (!ctx->bound) return fail(ctx, ENS_E_STATE, "ens_search_bound: call ens_bind first");
     if (!grid || !bounds || !de || !out) return fail(ctx, ENS_E_INVALID, "ens_search: null argument");
     if (grid->struct_size < sizeof(ens_t0_grid) || bounds->struct_size < sizeof(ens_bounds) ||
         de->struct_size < sizeof(ens_de_cfg) || out->struct_size < sizeof(ens_result))
@@ -654,6 +795,7 @@ ens_status ens_search(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bounds *b
                         (fixed_dense < 0 || dn == fixed_dense))
                         HIP_OR_FAIL(ctx, trial(ns_best, od, dn));
             ctx->tune_cache[key] = {nsl, order, dense};
+            if (!ctx->device_tag.empty()) save_tune_entry(ctx, key, ctx->tune_cache[key]);
         }
         ctx->stats.waves_used[kind] = nsl;
         ctx->stats.order_used[kind] = order;

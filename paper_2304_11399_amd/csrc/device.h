@@ -227,6 +227,7 @@ __device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
 template <typename R>
 struct CmpTerm {
     R part;
+    R Q;          // n0^2 + part: q = Q + ga h^2
     R dm;
     bool in_ap;
 };
@@ -238,6 +239,7 @@ __device__ __forceinline__ CmpTerm<R> cmp_term(const Cand<R> &cand, int32_t c, R
     const int32_t dc = c - cand.j;
     t.dm = static_cast<R>(dc) * dx;
     t.part = fmadd(cand.be, t.dm * t.dm, cand.al * t.dm);
+    t.Q = cand.n0sq + t.part;
     t.in_ap = dc <= cand.ap && -dc <= cand.ap;
     return t;
 }
@@ -325,6 +327,93 @@ __device__ __forceinline__ void accum_trace(Acc<W, R> &acc, const Cand<R> &c, co
             a = fmadd(wb, static_cast<R>(u[k + 1]), wa * static_cast<R>(u[k]));
         acc.s[k] += a;
         acc.E = fmadd(a, a, acc.E);
+    }
+}
+
+// A VALU instruction may read the result of v_dot2_f32_f16 only three wait
+// states after it.  The compiler counts them for its own instructions but not
+// for inline assembly, so every dot result passes through one s_nop 2 (three
+// wait states) before anything reads it.
+template <int W>
+__device__ __forceinline__ void dot_results_ready(float *a)
+{
+    static_assert(W % 2 == 1 && W >= 3 && W <= 15, "odd window, 3..15");
+    if constexpr (W == 3) {
+        asm volatile("s_nop 2" : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]));
+    } else if constexpr (W == 5) {
+        asm volatile("s_nop 2" : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(a[4]));
+    } else if constexpr (W == 7) {
+        asm volatile("s_nop 2" : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(a[4]), "+v"(a[5]),
+                     "+v"(a[6]));
+    } else {
+        // longer windows: the first seven, then the rest
+        asm volatile("s_nop 2" : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(a[4]), "+v"(a[5]),
+                     "+v"(a[6]));
+        dot_results_ready<W - 6>(a + 6);
+    }
+}
+
+// Binary16 windows through packed dot products.  The traveltime in samples
+// tau = sqrt(q) is rounded to the grid of spacing 2^-11 (B = 4096; coarser for
+// longer records) by one binary32 addition: y = tau + B + PAD - W/2 lies in
+// [B, 2B), where binary32 values are spaced by the grid.  floor(y) - B is the
+// window's first column and wb = y - floor(y), wa = 1 - wb are exact multiples
+// of the grid, hence exact in binary16, as are their products with the
+// trace's power-of-two weight scale.  Each interpolated sample is then one
+// v_dot2_f32_f16 of the stored pair (u_k, u_k+1) with (wa, wb): binary16
+// products are exact in binary32, so a_k carries no rounding beyond the
+// binary32 sum.  Pairs (u_k, u_k+1) with k odd straddle two dwords and are
+// taken with alignbit.  A trace that does not take part (q < 0, tau > nt - 1,
+// outside the aperture) gets zero weights, which also clears whatever the
+// window load returned.
+template <int W>
+__device__ __forceinline__ void accum_trace_f16(Acc<W, float> &acc, const CmpTerm<float> &ct, float ga, float h2,
+                                                const uint16_t *__restrict__ row, uint32_t copy1, uint32_t row_bytes,
+                                                uint32_t wsc, const float kq, uint32_t bbits, uint32_t shift,
+                                                float tau_max)
+{
+    typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+    constexpr int ND = (W + 1) / 2;
+    const float q = fmadd(ga, h2, ct.Q);
+    const float tau = fast_sqrt(q);
+    const bool ok = ct.in_ap && tau <= tau_max;   // false for a NaN (q < 0)
+    const float y = tau + kq;
+    const float fl = floor_r(y);
+    const float wb = y - fl;
+    const float wa = 1.0f - wb;
+    const uint32_t off = (__float_as_uint(fl) - bbits) >> shift;   // 2 * column, in bytes
+    const uint32_t start = off + __umul24(off & 2u, copy1 - 1u);
+    half2_t w = __builtin_bit_cast(half2_t, __builtin_amdgcn_cvt_pkrtz(wa, wb));
+    w = w * __builtin_bit_cast(half2_t, wsc);
+    const uint32_t wbits = ok ? __builtin_bit_cast(uint32_t, w) : 0u;
+    acc.M += ok ? 1 : 0;
+    const __amdgpu_buffer_rsrc_t rs = row_buffer(row, row_bytes);
+    uint32_t d[ND];
+    int m = 0;
+#pragma unroll
+    for (; m + 4 <= ND; m += 4) {
+        const u4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, start + 4u * m, 0, 0);
+        d[m] = v.x; d[m + 1] = v.y; d[m + 2] = v.z; d[m + 3] = v.w;
+    }
+    if constexpr (ND % 4 >= 2) {
+        const u2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, start + 4u * m, 0, 0);
+        d[m] = v.x; d[m + 1] = v.y;
+        m += 2;
+    }
+    if constexpr (ND % 2 == 1) d[m] = __builtin_amdgcn_raw_buffer_load_b32(rs, start + 4u * m, 0, 0);
+    float a[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        const uint32_t pr = (k & 1) ? __builtin_amdgcn_alignbit(d[k / 2 + 1], d[k / 2], 16) : d[k / 2];
+        // the three-operand form with an inline zero (the two-operand form the
+        // compiler picks for a zero accumulator costs a register clear each)
+        asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(a[k]) : "v"(pr), "v"(wbits));
+    }
+    dot_results_ready<W>(a);
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        acc.s[k] += a[k];
+        acc.E = fmadd(a[k], a[k], acc.E);
     }
 }
 

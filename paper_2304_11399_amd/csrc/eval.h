@@ -1,0 +1,163 @@
+// Semblance accumulation shared by the kernels of libens: wave helpers, the
+// trace loop over a candidate's aperture, and the compile-time dispatch
+// macros of the launch wrappers.
+#pragma once
+
+#include "device.h"
+#include "launch.h"
+
+namespace ens {
+
+// ---------------------------------------------------------------------------
+// wave helpers
+
+template <typename T>
+__device__ __forceinline__ T wave_min(T v)
+{
+    for (int off = WAVE / 2; off > 0; off >>= 1) {
+        const T o = __shfl_xor(v, off, WAVE);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_max(T v)
+{
+    for (int off = WAVE / 2; off > 0; off >>= 1) {
+        const T o = __shfl_xor(v, off, WAVE);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+    for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+    return v;
+}
+
+// Union of the lanes' aperture CMP ranges (wave-uniform; empty: c_hi < c_lo).
+__device__ __forceinline__ void wave_cmp_range(const StoreView &sv, int32_t j, int32_t ap, bool live,
+                                               int32_t &c_lo, int32_t &c_hi)
+{
+    int32_t lo = j - ap < 0 ? 0 : j - ap;
+    int32_t hi = j + ap > sv.n_cmp - 1 ? sv.n_cmp - 1 : j + ap;
+    if (!live) {
+        lo = 0x7fffffff;
+        hi = -1;
+    }
+    c_lo = __builtin_amdgcn_readfirstlane(wave_min(lo));
+    c_hi = __builtin_amdgcn_readfirstlane(wave_max(hi));
+}
+
+template <typename R>
+__device__ __forceinline__ R h2_of(const ENS_CONST_AS TraceMeta *meta, int32_t i)
+{
+    if constexpr (sizeof(R) == 8) {
+        const R h = static_cast<R>(meta[i].h);
+        return h * h;
+    } else {
+        return meta[i].h2;
+    }
+}
+
+// Window sums of one candidate over the traces of CMPs c_lo..c_hi; in each
+// CMP the traces first, first + step, first + 2 step, ... (two per step of
+// the loop, so that their gathers are in flight together).
+template <int DT, int W, bool SCALED, typename R>
+__device__ __forceinline__ void accumulate_cmps(const StoreView &sv, const Cand<R> &cand, int32_t c_lo,
+                                                int32_t c_hi, int32_t first, int32_t step,
+                                                Acc<W, R> &acc)
+{
+    using T = typename Store<DT>::T;
+    const T *store = static_cast<const T *>(sv.store);
+    const ENS_CONST_AS int64_t *cmp_ptr = const_view(sv.cmp_ptr);
+    const ENS_CONST_AS TraceMeta *meta = const_view(sv.meta);
+    const ENS_CONST_AS float *scale = const_view(sv.scale);
+    const R dx = static_cast<R>(sv.dx);
+    const uint32_t row_bytes = static_cast<uint32_t>(sv.ld * static_cast<int64_t>(sizeof(T)));
+    if constexpr (DT == DT_F16 && sizeof(R) == 4) {
+        const ENS_CONST_AS uint32_t *wsc = const_view(sv.wsc16);
+        // kq and bbits in vector registers: a scalar operand halves the issue
+        // rate of the addition and subtraction that use them
+        float kq;
+        uint32_t bbits;
+        asm("v_mov_b32 %0, %1" : "=v"(kq) : "s"(sv.h16_kq));
+        asm("v_mov_b32 %0, %1" : "=v"(bbits) : "s"(sv.h16_bbits));
+        const float tau_max = sv.tau_max;
+        const uint32_t shift = sv.h16_shift;
+        for (int32_t c = c_lo; c <= c_hi; ++c) {
+            const CmpTerm<R> ct = cmp_term(cand, c, dx);
+            const int32_t i1 = static_cast<int32_t>(cmp_ptr[c + 1]);
+            int32_t i = static_cast<int32_t>(cmp_ptr[c]) + first;
+            for (; i + step < i1; i += 2 * step) {
+                const int32_t i2 = i + step;
+                accum_trace_f16<W>(acc, ct, cand.ga, meta[i].h2, store + static_cast<size_t>(i) * sv.ld, sv.copy1,
+                                   row_bytes, wsc[i], kq, bbits, shift, tau_max);
+                accum_trace_f16<W>(acc, ct, cand.ga, meta[i2].h2, store + static_cast<size_t>(i2) * sv.ld,
+                                   sv.copy1, row_bytes, wsc[i2], kq, bbits, shift, tau_max);
+            }
+            if (i < i1)
+                accum_trace_f16<W>(acc, ct, cand.ga, meta[i].h2, store + static_cast<size_t>(i) * sv.ld, sv.copy1,
+                                   row_bytes, wsc[i], kq, bbits, shift, tau_max);
+        }
+        return;
+    }
+    for (int32_t c = c_lo; c <= c_hi; ++c) {
+        const CmpTerm<R> ct = cmp_term(cand, c, dx);
+        const int32_t i1 = static_cast<int32_t>(cmp_ptr[c + 1]);
+        int32_t i = static_cast<int32_t>(cmp_ptr[c]) + first;
+        for (; i + step < i1; i += 2 * step) {
+            const int32_t i2 = i + step;
+            accum_trace<DT, W, SCALED>(acc, cand, ct, h2_of<R>(meta, i),
+                                       store + static_cast<size_t>(i) * sv.ld, sv.copy1, row_bytes,
+                                       SCALED ? scale[i] : 1.0f);
+            accum_trace<DT, W, SCALED>(acc, cand, ct, h2_of<R>(meta, i2),
+                                       store + static_cast<size_t>(i2) * sv.ld, sv.copy1, row_bytes,
+                                       SCALED ? scale[i2] : 1.0f);
+        }
+        if (i < i1)
+            accum_trace<DT, W, SCALED>(acc, cand, ct, h2_of<R>(meta, i),
+                                       store + static_cast<size_t>(i) * sv.ld, sv.copy1, row_bytes,
+                                       SCALED ? scale[i] : 1.0f);
+    }
+}
+
+template <int DT, int W, typename R>
+__device__ __forceinline__ void accumulate_range(const StoreView &sv, const Cand<R> &cand, int32_t c_lo,
+                                                 int32_t c_hi, int32_t first, int32_t step,
+                                                 Acc<W, R> &acc)
+{
+    if constexpr (DT == DT_F16)
+        accumulate_cmps<DT, W, true, R>(sv, cand, c_lo, c_hi, first, step, acc);
+    else if (sv.scale)
+        accumulate_cmps<DT, W, true, R>(sv, cand, c_lo, c_hi, first, step, acc);
+    else
+        accumulate_cmps<DT, W, false, R>(sv, cand, c_lo, c_hi, first, step, acc);
+}
+
+#define ENS_DISPATCH_W(window, ...)                        \
+    switch (window) {                                      \
+    case 3: { constexpr int W = 3; __VA_ARGS__; } break;   \
+    case 5: { constexpr int W = 5; __VA_ARGS__; } break;   \
+    case 7: { constexpr int W = 7; __VA_ARGS__; } break;   \
+    case 9: { constexpr int W = 9; __VA_ARGS__; } break;   \
+    case 11: { constexpr int W = 11; __VA_ARGS__; } break; \
+    case 13: { constexpr int W = 13; __VA_ARGS__; } break; \
+    case 15: { constexpr int W = 15; __VA_ARGS__; } break; \
+    default: return hipErrorInvalidValue;                  \
+    }
+
+#define ENS_DISPATCH_OP(op, ...)                           \
+    if ((op) == 1) { constexpr int OP = 1; __VA_ARGS__; }  \
+    else { constexpr int OP = 3; __VA_ARGS__; }
+
+#define ENS_DISPATCH_DT(dt, ...)                                           \
+    switch (dt) {                                                          \
+    case DT_F32: { constexpr int DT = DT_F32; __VA_ARGS__; } break;        \
+    case DT_F16: { constexpr int DT = DT_F16; __VA_ARGS__; } break;        \
+    case DT_BF16: { constexpr int DT = DT_BF16; __VA_ARGS__; } break;      \
+    default: return hipErrorInvalidValue;                                  \
+    }
+
+}  // namespace ens

@@ -20,6 +20,12 @@ struct StoreView {
     int32_t nt;
     float dt, dx;
     const int32_t *ap_tab;    // [nt] half-aperture per time index
+    // binary16 windows (see accum_trace_f16)
+    const uint32_t *wsc16;    // [n_tr] per-trace weight scale 2^(e_i - g) as a pair of binary16
+    float h16_kq;             // B + PAD - W/2: tau + h16_kq lies in [B, 2B), spacing = weight grid
+    uint32_t h16_bbits;       // bit pattern of the binary32 B
+    uint32_t h16_shift;       // (bits(floor(tau + h16_kq)) - h16_bbits) >> h16_shift = 2 * column
+    float tau_max;            // nt - 1
 };
 
 struct CandView {
@@ -80,10 +86,17 @@ struct PolishArgs {
 // launch wrappers (return hipSuccess or the launch error)
 hipError_t launch_store_f32(const float *src, int64_t ld_in, int64_t n_tr, int32_t nt, int64_t ld,
                             float *dst, hipStream_t s);
-// dual: each output row is two rows of ld_out, the second shifted by one sample
+// dual: each output row is two rows of ld_out, the second shifted by one sample;
+// exp_out (optional): per-trace scale exponent (INT32_MIN for a zero trace)
 hipError_t launch_quantize(const float *src, int64_t ld_in, int64_t n_tr, int32_t nt, int32_t dtype,
                            uint16_t *dst, int64_t ld_out, int32_t col0, float *scale, bool dual,
-                           hipStream_t s);
+                           int32_t *exp_out, hipStream_t s);
+// caller-quantised 16-bit rows into the dual padded layout (+ optional dequantised binary32 master)
+hipError_t launch_store16(const uint16_t *src, int64_t ld_in, int64_t n_tr, int32_t nt, int32_t dtype,
+                          const float *scale, uint16_t *dst, int64_t ld_out, float *master, int32_t *exp_out,
+                          hipStream_t s);
+// relative weight scales of a 16-bit store from the exponents k_quantize wrote
+hipError_t launch_relscale(const int32_t *e, int64_t n_tr, float *rel, uint32_t *wsc16, hipStream_t s);
 hipError_t launch_eval(int op, int dtype, int window, const StoreView &sv, const CandView &cv,
                        float *S, int32_t *M, hipStream_t s);
 hipError_t launch_eval64(int op, int window, const StoreView &sv_f32, const CandView &cv, double *S,

@@ -1,0 +1,6 @@
+// Search kernels of libens for bf16 trace storage (see search.h).
+#include "search.h"
+
+namespace ens {
+template hipError_t launch_search_dt<DT_BF16>(int, int, int, int, const SearchArgs &, int32_t, hipStream_t);
+}  // namespace ens

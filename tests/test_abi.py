@@ -37,7 +37,7 @@ def _ctx():
 
 def test_struct_sizes_match_header_layout():
     # int64 members force 8-byte alignment; the Python mirrors must agree
-    assert C.sizeof(ens.Traces) == 48
+    assert C.sizeof(ens.Traces) == 72
     assert C.sizeof(ens.DeCfg) == 68
     assert C.sizeof(ens.Result) == 56
     assert C.sizeof(ens.Stats) == 168
@@ -70,7 +70,8 @@ def test_null_and_state_errors():
     try:
         assert lib.ens_bind(h, None, None, None) == -1
         assert b"null" in lib.ens_last_error(h)
-        assert lib.ens_search(h, None, None, None, 0, None) == -6
+        assert lib.ens_search_bound(h, None, None, None, 0, None) == -6
+        assert lib.ens_search(h, None, None, None, None, None, None, 0, None) == -1
         c = ens._sized(ens.Candidates, n=0)
         assert lib.semblance_eval(h, C.byref(c), None, None) == -6
         assert lib.semblance_backward(h, C.byref(c), None, None) == -6
@@ -96,6 +97,7 @@ def _bind_args(**kw):
 @pytest.mark.parametrize("field,value,status", [
     ("window", 6, -2), ("window", 17, -2), ("op", 2, -1), ("store_dtype", 7, -1),
     ("nt", 1, -1), ("dt", 0.0, -2), ("dx", -1.0, -2), ("ap_lo", -1, -2), ("ld", 10, -1),
+    ("data_dtype", 5, -1),
 ])
 def test_bind_rejects_bad_arguments_before_any_device_call(field, value, status):
     lib, h = _ctx()
@@ -117,6 +119,19 @@ def test_bind_rejects_bad_geometry_and_struct_size():
         tr, geo, sem, keep = _bind_args()
         tr.struct_size = 8
         assert lib.ens_bind(h, C.byref(tr), C.byref(geo), C.byref(sem)) == -1
+    finally:
+        lib.ens_ctx_destroy(h)
+
+
+def test_sixteen_bit_data_need_scales_and_a_compatible_store():
+    lib, h = _ctx()
+    try:
+        tr, geo, sem, keep = _bind_args(data_dtype=1, store_dtype=1)
+        assert lib.ens_bind(h, C.byref(tr), C.byref(geo), C.byref(sem)) == -1     # no scale
+        assert b"scale" in lib.ens_last_error(h)
+        tr, geo, sem, keep = _bind_args(data_dtype=1, store_dtype=2)
+        tr.scale = 0x2000
+        assert lib.ens_bind(h, C.byref(tr), C.byref(geo), C.byref(sem)) == -5     # f16 into bf16
     finally:
         lib.ens_ctx_destroy(h)
 

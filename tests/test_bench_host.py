@@ -1,5 +1,6 @@
 """Host logic of bench.py (no GPU): the one-GPU guard, the flop count of
-the definition and the source check on the stored HBM-traffic figure."""
+the definition, the source and launch-shape check on the stored profile
+figures, and the default workload."""
 import json
 import os
 import shutil
@@ -27,22 +28,40 @@ def test_flops_per_pair_counts_the_definition():
     assert bench.flops_per_pair(1, 5) == 7 + 6 * 5 + 1
 
 
-def test_traffic_figure_is_dropped_once_the_kernel_sources_change(tmp_path, monkeypatch):
-    import hashlib
+def test_profile_figures_are_dropped_once_the_kernel_or_its_shape_changes(tmp_path):
     src = os.path.join(ROOT, "paper_2304_11399_amd", "csrc")
     dst = tmp_path / "paper_2304_11399_amd" / "csrc"
     dst.mkdir(parents=True)
-    h = hashlib.sha256()
-    for f in ("device.h", "kernels.hip"):
+    for f in bench.KERNEL_SOURCES:
         shutil.copy(os.path.join(src, f), dst / f)
-        h.update(open(dst / f, "rb").read())
     (tmp_path / "profiles").mkdir()
-    rec = {"workload": "w", "kernel": "k", "source_sha256": h.hexdigest(),
+    shape = {"waves": 2, "item_order": 3, "dense": 0}
+    rec = {"workload": "w", "kernel": "k", "shape": shape,
+           "source_sha256": bench.kernel_sources_sha(str(tmp_path)),
            "traffic_bytes_per_launch": 123.0}
     json.dump(rec, open(tmp_path / "profiles" / "w_traffic.json", "w"))
-    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.measured_traffic("w")["traffic_bytes_per_launch"] == 123.0
-    with open(dst / "kernels.hip", "a") as fh:
+    root = str(tmp_path)
+    assert bench.measured_profile("w", "k", shape, root)["traffic_bytes_per_launch"] == 123.0
+    # another launch shape, another kernel, or a missing record: no figure
+    assert bench.measured_profile("w", "k", dict(shape, item_order=1), root) is None
+    assert bench.measured_profile("w", "k2", shape, root) is None
+    assert bench.measured_profile("no_such_workload", "k", shape, root) is None
+    # any kernel source edited since the profile: no figure
+    with open(dst / "search.h", "a") as fh:
         fh.write("\n// changed\n")
-    assert bench.measured_traffic("w") is None
-    assert bench.measured_traffic("no_such_workload") is None
+    assert bench.measured_profile("w", "k", shape, root) is None
+
+
+def test_the_default_workload_is_the_binary16_polish_line():
+    args = sys.argv
+    try:
+        sys.argv = ["bench.py"]
+        a = bench.parse()
+    finally:
+        sys.argv = args
+    assert a.workload == "crs_diff"
+    from synth import WORKLOADS
+    wl = WORKLOADS["crs_diff"]
+    assert wl["store"] == "f16" and wl["de"]["polish_steps"] == 10
+    kinds = {v[0] for v in bench.variants_for("crs_diff", dict(wl, name="crs_diff"))}
+    assert {"ens_f16_polish", "ens_f16", "ens_f32", "plain_f32"} <= kinds

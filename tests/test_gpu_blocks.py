@@ -5,6 +5,7 @@ import pytest
 
 import oracle
 from synth import base_bounds, make_workload, random_candidates
+from tests._tol import s_tol
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -79,7 +80,7 @@ def _bound(ens, name, store="f32", **over):
     return ctx, g, wl
 
 
-def _compare(ctx, L, cmp, t, p, tol=TOL_S, label=""):
+def _compare(ctx, L, cmp, t, p, tol=TOL_S, label="", store="f32"):
     S, M = ctx.semblance_eval(_dev(cmp), _dev(t), _dev(p), with_M=True)
     S, M = S.cpu().numpy().astype(np.float64), M.cpu().numpy()
     S_or, M_or, margin = L.semblance(cmp, t, p.astype(np.float64))
@@ -89,9 +90,10 @@ def _compare(ctx, L, cmp, t, p, tol=TOL_S, label=""):
     assert flip.mean() < 1e-3, f"{label}: too many participation flips {flip.sum()}"
     ok = ~flip
     err = np.abs(S - S_or)[ok]
+    bound = s_tol(store, L, cmp, t, p)[ok] if store == "f16" else np.full(err.size, tol)
     print(f"{label}: n={len(cmp)} flips={flip.sum()} max|dS|={err.max():.2e} "
-          f"mean|dS|={err.mean():.2e}")
-    assert err.max() <= tol, f"{label}: max |S_gpu - S_oracle| = {err.max():.3e}"
+          f"mean|dS|={err.mean():.2e} max|dS|/bound={np.max(err / bound):.3f}")
+    assert np.all(err <= bound), f"{label}: max |S_gpu - S_oracle| / bound = {np.max(err / bound):.3e}"
     assert np.all((S >= 0) & (S <= 1.0 + 1e-6))
     return S, S_or
 
@@ -139,7 +141,7 @@ def test_semblance_reduced_precision_store(ens, store):
     Lq = oracle.Line.from_gather(g, wl["window"], wl["op"], wl["ap_lo"], wl["ap_hi"], traces=deq)
     L32 = oracle.Line.from_gather(g, wl["window"], wl["op"], wl["ap_lo"], wl["ap_hi"])
     cmp, t, p = random_candidates(8000, g.n_cmp, g.nt, g.dt, 3, base_bounds(wl), seed=7)
-    S, _ = _compare(ctx, Lq, cmp, t, p, label=f"{store} arithmetic")
+    S, _ = _compare(ctx, Lq, cmp, t, p, label=f"{store} arithmetic", store=store)
     S32, _, _ = L32.semblance(cmp, t, p.astype(np.float64))
     total = np.abs(S - S32)
     print(f"{store}: total error vs binary64 on the binary32 traces: max {total.max():.2e}")

@@ -9,6 +9,7 @@ import pytest
 
 import oracle
 from synth import base_bounds, make_workload
+from tests._tol import s_tol
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -36,7 +37,7 @@ def _line(ens, name, store, **over):
     return ctx, g, wl, L
 
 
-def _check(ctx, g, wl, L, de, seed, t0, t1, label):
+def _check(ctx, g, wl, L, de, seed, t0, t1, label, store="f32"):
     bounds = base_bounds(wl)
     out = ctx.search(bounds, de, seed=seed, t_begin=t0, t_end=t1)
     p_or, S_run, ev = L.search(bounds, de, seed, t_begin=t0, t_end=t1)
@@ -48,14 +49,18 @@ def _check(ctx, g, wl, L, de, seed, t0, t1, label):
     S = out["S"].cpu().numpy().reshape(-1).astype(np.float64)
     S_or, _, margin = L.semblance(cmp, t, p.astype(np.float64))
     ok = margin >= 0.05
-    err = np.abs(S - S_or)[ok].max() if ok.any() else 0.0
+    bound = s_tol(store, L, cmp[ok], t[ok], p[ok])
+    err = np.abs(S - S_or)[ok]
     same = np.all(p == p_or.reshape(-1, P), axis=1).mean()
-    print(f"{label}: evals {ev}, max|S - S_oracle(p)| {err:.2e}, identical {same:.3f}, "
-          f"mean S gpu {S.mean():.5f} oracle run {S_run.mean():.5f}")
-    assert err <= TOL_S
-    # the same draws and the same decisions up to binary32 ties: 99-100% of
-    # the samples end on bitwise the oracle's parameters
-    assert same >= 0.95
+    print(f"{label}: evals {ev}, max|S - S_oracle(p)| {err.max():.2e} ({np.max(err / bound):.3f} "
+          f"of the bound), identical {same:.3f}, mean S gpu {S.mean():.5f} oracle run {S_run.mean():.5f}")
+    assert np.all(err <= bound)
+    # the same draws and the same decisions up to ties: with binary32
+    # windows 99-100% of the samples end on bitwise the oracle's parameters;
+    # binary16 windows round traveltimes to 2^-11 samples, which moves S by
+    # up to ~1e-5 and flips more selections between near-equal members (a
+    # flip changes the rest of that sample's trajectory)
+    assert same >= (0.8 if store == "f16" else 0.95)
     assert abs(S.mean() - S_run.mean()) < 2e-3
     return out
 
@@ -70,7 +75,7 @@ def test_jade_with_time_skipping(ens, n_skip):
 def test_jade_on_binary16_traces(ens):
     ctx, g, wl, L = _line(ens, "crs_ens", "f16", n_cmp=12, nt=240)
     de = dict(wl["de"], np_lo=16, np_hi=16, ng_f=10, n_bucket=6, adapt=1, CR=0.5)
-    _check(ctx, g, wl, L, de, 42, 10, 230, "jade f16")
+    _check(ctx, g, wl, L, de, 42, 10, 230, "jade f16", store="f16")
 
 
 def test_cmp_operator_with_jade_and_skipping(ens):

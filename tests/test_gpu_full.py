@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests._tol import s_tol
 from paper_2304_11399_amd.counts import evals_ens
 from synth import base_bounds, make_workload
 
@@ -65,16 +66,19 @@ def test_full_size_workload(ens, name, store):
         traces = oracle.dequantize(q, s, store)
     Lq = oracle.Line.from_gather(g, wl["window"], wl["op"], wl["ap_lo"], wl["ap_hi"], traces=traces)
     S_q, _, margin = Lq.semblance(cmp, t, p)
-    err = np.abs(S - S_q)[margin >= 0.05]
+    sel = margin >= 0.05
+    err = np.abs(S - S_q)[sel]
+    bound = s_tol(store, Lq, cmp[sel], t[sel], p[sel])
     del Lq
     L32 = oracle.Line.from_gather(g, wl["window"], wl["op"], wl["ap_lo"], wl["ap_hi"])
     S_32, _, margin32 = L32.semblance(cmp, t, p)
     S64 = out["S64"].cpu().numpy()
     err64 = np.abs(S64.reshape(-1)[pick] - S_32)[margin32 > 1e-6]
     gap = _gap(name, S64, g)
-    print(f"{name} {store}: max|S - S_oracle(stored)| {err.max():.2e}; max|S64 - S_oracle| "
-          f"{err64.max():.2e}; mean gap {gap.mean():.2e} ({np.mean(gap <= 1e-3):.3f} <= 1e-3)")
-    assert err.max() <= TOL_S
+    print(f"{name} {store}: max|S - S_oracle(stored)| {err.max():.2e} ({np.max(err / bound):.3f} of the "
+          f"bound); max|S64 - S_oracle| {err64.max():.2e}; mean gap {gap.mean():.2e} "
+          f"({np.mean(gap <= 1e-3):.3f} <= 1e-3)")
+    assert np.all(err <= bound)
     assert err64.max() < 1e-11
     assert gap.mean() <= 1e-3
     if de.get("polish_steps", 0) > 0:

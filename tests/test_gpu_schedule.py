@@ -4,6 +4,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests._tol import s_tol
 from paper_2304_11399_amd.counts import evals_ens
 from synth import base_bounds, make_workload
 
@@ -119,7 +120,7 @@ def test_reduced_precision_search(ens, store):
     S = out["S"].cpu().numpy().reshape(-1)
     Sq, _, margin = Lq.semblance(cmp, t, p)
     ok = margin >= 0.05
-    assert np.abs(S - Sq)[ok].max() <= 1e-5          # arithmetic on the stored values
+    assert np.all(np.abs(S - Sq)[ok] <= s_tol(store, Lq, cmp[ok], t[ok], p[ok]))  # arithmetic on the stored values
     S32, _, margin32 = L32.semblance(cmp, t, p)
     S64 = out["S64"].cpu().numpy().reshape(-1)
     assert np.abs(S64 - S32)[margin32 > 1e-6].max() < 1e-11  # re-score on the binary32 master

@@ -120,10 +120,16 @@ def _awkward_values(n=4096, seed=0):
 def test_quantiser_matches_library_rounding(dtype):
     u = _awkward_values()
     q, s = oracle.quantize(u, dtype)
-    s_ref = np.abs(u).max(axis=1)
-    s_ref[s_ref == 0] = 1.0
-    np.testing.assert_array_equal(s, s_ref)
+    peak = np.abs(u).max(axis=1).astype(np.float64)
+    # the scale is a power of two with peak <= s < 2 peak (1 for the zero trace)
+    mant, _ = np.frexp(s)
+    assert np.all(mant == 0.5)
+    nz = peak > 0
+    assert np.all((peak[nz] <= s[nz]) & (s[nz] < 2 * peak[nz])) and np.all(s[~nz] == 1.0)
+    s_ref = s
     x = (u / s_ref[:, None]).astype(np.float32)
+    # division by a power of two is exact (no binary32 underflow here)
+    np.testing.assert_array_equal(x.astype(np.float64) * s_ref[:, None], u.astype(np.float64))
     if dtype == "f16":
         ref = x.astype(np.float16).view(np.uint16)          # numpy: round to nearest even
     else:
@@ -205,3 +211,53 @@ def test_sref_against_fine_brute_force_cmp():
                               np.full(fine.size, t[c], np.int32), fine[:, None])
         assert S_ref[c] >= S.max() - 1e-4
         assert S_ref[c] <= 1.0
+
+
+# ---------------------------------------------------------------- traveltime sensitivity
+def test_traveltime_sensitivity_is_the_sum_of_per_trace_derivatives():
+    # per-trace derivatives by finite differences of the oracle's S in each
+    # trace's offset alone (CMP operator: dtau_i/dh_i = C h_i / (t_i dt))
+    rng = np.random.default_rng(5)
+    nt, dt = 160, float(np.float32(0.004))
+    offs = np.sort(rng.uniform(50.0, 900.0, 10))
+    kern = np.exp(-0.5 * (np.arange(-6, 7) / 2.0) ** 2)
+    tr = np.array([np.convolve(rng.standard_normal(nt), kern, mode="same") for _ in offs])
+    C, n0 = 1.0 / 2200.0 ** 2, 70
+    L = _tiny.line(tr, [offs.size], offs, dt=dt, window=7)
+    l1 = L.tau_sensitivity([0], [n0], [[C]])[0]
+    total, checked = 0.0, 0
+    for i, h in enumerate(offs):
+        t_i = np.sqrt((n0 * dt) ** 2 + C * h * h)
+        dtau_dh = C * h / (t_i * dt)
+        fd = []
+        for eps in (1e-6 * h, 0.5e-6 * h):
+            op, om = offs.copy(), offs.copy()
+            op[i] += eps
+            om[i] -= eps
+            Sp = _tiny.line(tr, [offs.size], op, dt=dt, window=7).semblance([0], [n0], [[C]])[0][0]
+            Sm = _tiny.line(tr, [offs.size], om, dt=dt, window=7).semblance([0], [n0], [[C]])[0][0]
+            fd.append((Sp - Sm) / (2 * eps) / dtau_dh)
+        assert abs(fd[0] - fd[1]) <= 1e-4 * max(abs(fd[1]), 1e-6)   # no interpolation kink inside
+        total += abs(fd[1])
+        checked += 1
+    assert checked == offs.size and l1 > 0
+    assert abs(l1 - total) <= 1e-5 * total
+
+
+def test_traveltime_sensitivity_vanishes_for_one_trace_and_bounds_the_gradient():
+    # M = 1: S = 1 whatever the traveltime
+    tr = np.sin(np.arange(100) * 0.3)[None, :]
+    L1 = _tiny.line(tr, [1], [300.0], window=5)
+    assert L1.tau_sensitivity([0], [40], [[1.0 / 2000.0 ** 2]])[0] == 0.0
+    # chain rule and the triangle inequality: |dS/dC| <= max_i dtau_i/dC * sum_i |dS/dtau_i|,
+    # and dtau_i/dC = h_i^2 / (2 t_i dt) <= h_max^2 / (2 t0 dt) for C > 0
+    g, wl = make_workload("cmp_small")
+    L = oracle.Line.from_gather(g, wl["window"], wl["op"], wl["ap_lo"], wl["ap_hi"])
+    cmp, t, p = random_candidates(300, g.n_cmp, g.nt, g.dt, 1, base_bounds(wl), seed=21,
+                                  t_range=(20, 240))
+    _, grad = L.semblance_grad(cmp, t, p.astype(np.float64))
+    l1 = L.tau_sensitivity(cmp, t, p)
+    dt = float(np.float32(g.dt))
+    bound = np.max(g.offset) ** 2 / (2 * t * dt * dt) * l1
+    assert np.all(np.abs(grad[:, 0]) <= bound * (1 + 1e-9) + 1e-15)
+    assert np.mean(l1 > 0) > 0.99
