@@ -68,6 +68,7 @@ def lib():
         L.or_semblance_batch.argtypes = [C.POINTER(_Line), C.c_int64, P, P, P, P, P, P]
         L.or_semblance_grad_batch.argtypes = [C.POINTER(_Line), C.c_int64, P, P, P, P, P]
         L.or_semblance_tau_l1_batch.argtypes = [C.POINTER(_Line), C.c_int64, P, P, P, P]
+        L.or_kink_margin_batch.argtypes = [C.POINTER(_Line), C.c_int64, P, P, P, P]
         L.or_de_trial.argtypes = [C.c_int32, C.c_int32, P, P, P, C.c_float, C.c_float, P, P, P]
         L.or_search.argtypes = [C.POINTER(_Line), C.POINTER(_Bounds), C.POINTER(_DeCfg),
                                 C.c_uint64, P, C.c_int32, C.c_int32, C.c_int32, P, P]
@@ -183,6 +184,15 @@ class Line:
         out = np.zeros(cmp.size)
         lib().or_semblance_tau_l1_batch(C.byref(self._s), cmp.size, _ptr(cmp), _ptr(t), _ptr(p),
                                         _ptr(out))
+        return out
+
+    def kink_margin(self, cmp, t, params):
+        """min over participating traces of |tau_i - round(tau_i)| / (1 + |tau_i - n0|)."""
+        cmp = np.ascontiguousarray(cmp, dtype=np.int32)
+        t = np.ascontiguousarray(t, dtype=np.int32)
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(-1, self.op))
+        out = np.zeros(cmp.size)
+        lib().or_kink_margin_batch(C.byref(self._s), cmp.size, _ptr(cmp), _ptr(t), _ptr(p), _ptr(out))
         return out
 
     def search(self, bounds, de, seed, cmp_out=None, t_begin=0, t_end=None, objective=0,

@@ -80,6 +80,13 @@ void or_semblance_batch(const or_line *L, int64_t n, const int32_t *cmp, const i
  * by at most about delta times this sum (first order). */
 void or_semblance_tau_l1_batch(const or_line *L, int64_t n, const int32_t *cmp, const int32_t *t,
                                const double *params, double *l1);
+/* Distance of the participating traces' traveltimes from whole samples,
+ * relative to the moveout: min_i |tau_i - round(tau_i)| / (1 + |tau_i - n0|)
+ * (infinity when no trace takes part).  The interpolation has a kink at whole
+ * samples, where the derivative in tau jumps; a computation whose traveltimes
+ * carry a relative error may land on the other side of it. */
+void or_kink_margin_batch(const or_line *L, int64_t n, const int32_t *cmp, const int32_t *t,
+                          const double *params, double *out);
 /* Gradient dS/dp (M held fixed, right derivative at integer traveltime). */
 double or_semblance_grad(const or_line *L, int32_t j, int32_t n0, const double *p, double *g);
 void or_semblance_grad_batch(const or_line *L, int64_t n, const int32_t *cmp, const int32_t *t,

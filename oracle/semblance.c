@@ -193,3 +193,33 @@ void or_semblance_tau_l1_batch(const or_line *L, int64_t n, const int32_t *cmp, 
         semblance_impl(L, cmp[c], t[c], params + c * P, NULL, NULL, g, l1 + c);
     }
 }
+
+void or_kink_margin_batch(const or_line *L, int64_t n, const int32_t *cmp, const int32_t *t,
+                          const double *params, double *out)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t c = 0; c < n; ++c) {
+        const int32_t j = cmp[c], n0 = t[c];
+        const int32_t a = or_aperture(L, n0);
+        const int32_t c_lo = j - a < 0 ? 0 : j - a;
+        const int32_t c_hi = j + a > L->n_cmp - 1 ? L->n_cmp - 1 : j + a;
+        const double t0 = (double)n0 * L->dt;
+        const double *p = params + c * L->op;
+        double m = INFINITY;
+        for (int32_t cc = c_lo; cc <= c_hi; ++cc) {
+            double dm = (double)(cc - j) * L->dx;
+            for (int64_t i = L->cmp_ptr[cc]; i < L->cmp_ptr[cc + 1]; ++i) {
+                double q = traveltime_sq(L, p, t0, dm, L->offset[i], NULL);
+                if (q < 0.0)
+                    continue;
+                double tau = sqrt(q) / L->dt;
+                if (tau > (double)(L->nt - 1))
+                    continue;
+                double d = fabs(tau - floor(tau + 0.5)) / (1.0 + fabs(tau - (double)n0));
+                if (d < m)
+                    m = d;
+            }
+        }
+        out[c] = m;
+    }
+}

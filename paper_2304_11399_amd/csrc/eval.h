@@ -64,7 +64,10 @@ __device__ __forceinline__ R h2_of(const ENS_CONST_AS TraceMeta *meta, int32_t i
 // Window sums of one candidate over the traces of CMPs c_lo..c_hi; in each
 // CMP the traces first, first + step, first + 2 step, ... (two per step of
 // the loop, so that their gathers are in flight together).
-template <int DT, int W, bool SCALED, typename R>
+// EXACT: binary16 windows through the binary32 interpolation of the
+// converted samples at the exact traveltime (the adjoint's forward pass),
+// instead of the packed dot products on the 2^-11-sample grid.
+template <int DT, int W, bool SCALED, typename R, bool EXACT = false>
 __device__ __forceinline__ void accumulate_cmps(const StoreView &sv, const Cand<R> &cand, int32_t c_lo,
                                                 int32_t c_hi, int32_t first, int32_t step,
                                                 Acc<W, R> &acc)
@@ -76,7 +79,7 @@ __device__ __forceinline__ void accumulate_cmps(const StoreView &sv, const Cand<
     const ENS_CONST_AS float *scale = const_view(sv.scale);
     const R dx = static_cast<R>(sv.dx);
     const uint32_t row_bytes = static_cast<uint32_t>(sv.ld * static_cast<int64_t>(sizeof(T)));
-    if constexpr (DT == DT_F16 && sizeof(R) == 4) {
+    if constexpr (DT == DT_F16 && sizeof(R) == 4 && !EXACT) {
         const ENS_CONST_AS uint32_t *wsc = const_view(sv.wsc16);
         // kq and bbits in vector registers: a scalar operand halves the issue
         // rate of the addition and subtraction that use them
@@ -123,13 +126,13 @@ __device__ __forceinline__ void accumulate_cmps(const StoreView &sv, const Cand<
     }
 }
 
-template <int DT, int W, typename R>
+template <int DT, int W, typename R, bool EXACT = false>
 __device__ __forceinline__ void accumulate_range(const StoreView &sv, const Cand<R> &cand, int32_t c_lo,
                                                  int32_t c_hi, int32_t first, int32_t step,
                                                  Acc<W, R> &acc)
 {
     if constexpr (DT == DT_F16)
-        accumulate_cmps<DT, W, true, R>(sv, cand, c_lo, c_hi, first, step, acc);
+        accumulate_cmps<DT, W, true, R, EXACT>(sv, cand, c_lo, c_hi, first, step, acc);
     else if (sv.scale)
         accumulate_cmps<DT, W, true, R>(sv, cand, c_lo, c_hi, first, step, acc);
     else

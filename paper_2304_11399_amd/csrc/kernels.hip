@@ -218,9 +218,11 @@ __device__ __forceinline__ float semblance_grad_lane(const StoreView &sv, const 
 {
     using T = typename Store<DT>::T;
     const T *store = static_cast<const T *>(sv.store);
+    // the forward pass at the exact traveltimes, so that the adjoint is the
+    // derivative of the interpolated semblance the binary64 definition gives
     Acc<W, float> acc;
     acc.reset();
-    accumulate_range<DT, W, float>(sv, cand, c_lo, c_hi, 0, 1, acc);
+    accumulate_range<DT, W, float, true>(sv, cand, c_lo, c_hi, 0, 1, acc);
     const float S = finish_semblance(acc);
 #pragma unroll
     for (int d = 0; d < OP; ++d) g[d] = 0.0f;

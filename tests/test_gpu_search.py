@@ -83,10 +83,23 @@ def test_plain_de_cmp_small_matches_oracle(ens):
     gap_or = np.maximum(S_ref - S_or_run.reshape(-1), 0)
     print(f"gap mean {gap.mean():.2e} p95 {np.quantile(gap, 0.95):.2e} max {gap.max():.2e}; "
           f"oracle run gap mean {gap_or.mean():.2e}")
-    # the device search is as good as the oracle's own run of the same budget
-    # (whether the budget reaches a 1e-3 mean gap is a property of NP x NG)
+    # the device search is as good as the oracle's own run of the same budget;
+    # at the configured NP 16 x NG 30 that is a mean gap just above 1e-3 (a few
+    # populations settle on side maxima, and more generations do not move them)
     assert abs(gap.mean() - gap_or.mean()) <= 2e-4
-    assert np.median(gap) <= 1e-4 and gap.mean() <= 2e-3
+    assert np.median(gap) <= 1e-4
+    # the raised budget, NP 24 x NG 30 (a larger population, the same
+    # generations), reaches the 1e-3 bar on the device and in the oracle
+    raised = dict(de, np_lo=24, np_hi=24)
+    out24 = ctx.search(bounds, raised, seed=wl["search_seed"])
+    assert out24["n_evals"] == evals_jade(P_d, 24, 30)
+    _check_scores(out24, L, cmp, t, 1, "cmp_small plain DE 24x30")
+    _, S_or24, _ = L.search(bounds, raised, wl["search_seed"])
+    gap24 = np.maximum(S_ref - out24["S64"].cpu().numpy().reshape(-1), 0)
+    gap24_or = np.maximum(S_ref - S_or24.reshape(-1), 0)
+    print(f"NP 24 x NG 30: gap mean {gap24.mean():.2e} (oracle run {gap24_or.mean():.2e}), "
+          f"{np.mean(gap24 <= 1e-3):.3f} <= 1e-3")
+    assert gap24.mean() <= 1e-3 and gap24_or.mean() <= 1e-3
 
 
 def test_search_is_deterministic_and_sliced_variants_agree(ens):
@@ -119,7 +132,9 @@ def test_ens_small_matches_oracle(ens):
     same = np.all(p == p_or.reshape(-1, 3), axis=1)
     print(f"ENS identical trajectories: {same.mean():.4f}; mean S gpu {S.mean():.5f} "
           f"oracle {S_run.mean():.5f}")
+    # the same draws and decisions up to binary32 ties (97-98% measured), and
     # both searches reach the same quality
+    assert same.mean() >= 0.95
     assert abs(S.mean() - S_run.mean()) < 2e-3
 
 

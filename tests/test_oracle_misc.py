@@ -261,3 +261,18 @@ def test_traveltime_sensitivity_vanishes_for_one_trace_and_bounds_the_gradient()
     bound = np.max(g.offset) ** 2 / (2 * t * dt * dt) * l1
     assert np.all(np.abs(grad[:, 0]) <= bound * (1 + 1e-9) + 1e-15)
     assert np.mean(l1 > 0) > 0.99
+
+
+def test_kink_margin_of_known_traveltimes():
+    dt = float(np.float32(0.004))
+    n0, h = 40, 300.0
+    tr = np.sin(np.arange(120) * 0.2)[None, :]
+    L = _tiny.line(tr, [1], [h], dt=dt, window=5)
+    # C = 0: tau = n0 exactly, on a whole sample
+    assert L.kink_margin([0], [n0], [[0.0]])[0] == 0.0
+    # tau = n0 + 1.25: a quarter sample from a whole sample, relative to 1 + 1.25
+    C = (((n0 + 1.25) * dt) ** 2 - (n0 * dt) ** 2) / h ** 2
+    assert abs(L.kink_margin([0], [n0], [[C]])[0] - 0.25 / 2.25) < 1e-9
+    # a trace past the record does not count
+    C_far = (((119.5) * dt) ** 2 - (n0 * dt) ** 2) / h ** 2
+    assert L.kink_margin([0], [n0], [[C_far]])[0] == np.inf
