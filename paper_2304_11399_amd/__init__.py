@@ -122,6 +122,7 @@ _SIGS = {
                              C.POINTER(T0Grid), C.POINTER(Bounds), C.POINTER(DeCfg), C.c_uint64,
                              C.POINTER(Result)]),
     "ens_stack": (C.c_int, [_P, C.POINTER(T0Grid), _P, _P, _P, C.POINTER(C.c_double)]),
+    "ens_stack_noalloc": (C.c_int, [_P, C.POINTER(T0Grid), _P, _P, _P, C.POINTER(C.c_double)]),
     "ens_jade_draws": (C.c_int, [_P, C.c_int64, _P, C.c_double, C.c_double, C.c_int32, _P, _P, _P]),
     "semblance_eval": (C.c_int, [_P, C.POINTER(Candidates), _P, _P]),
     "semblance_eval64": (C.c_int, [_P, C.POINTER(Candidates), _P]),
@@ -334,9 +335,11 @@ class Context:
         self._bound_as(traces, cmp_ptr, op)
         return dict(outs, n_evals=int(res.n_evals), sum_m=int(res.sum_m))
 
-    def stack(self, params, S=None, cmp_out=None, t_begin=0, t_end=None):
+    def stack(self, params, S=None, cmp_out=None, t_begin=0, t_end=None, out=None, noalloc=False):
         """Zero-offset stack along each sample's operator (device [n_out, n_t]),
-        and the RMS of the coherence panel S when S is given (else None)."""
+        and the RMS of the coherence panel S when S is given (else None).
+        noalloc: through ens_stack_noalloc (no device allocation in the
+        library; out, a caller tensor, receives the stack)."""
         import torch
         _require_cuda(params, S)
         t_end = self.nt if t_end is None else int(t_end)
@@ -349,10 +352,13 @@ class Context:
         co = None if cmp_out is None else np.ascontiguousarray(cmp_out, dtype=np.int32)
         grid = _sized(T0Grid, cmp_out=None if co is None else co.ctypes.data, n_cmp_out=n_out,
                       t_begin=int(t_begin), t_end=t_end)
-        out = torch.empty((n_out, n_t), dtype=torch.float32, device=params.device)
+        if out is None:
+            out = torch.empty((n_out, n_t), dtype=torch.float32, device=params.device)
+        assert out.dtype == torch.float32 and out.is_contiguous() and out.numel() == n_out * n_t
         rms = C.c_double(0.0)
-        self._check(self._lib.ens_stack(self._h, C.byref(grid), _ptr(params), _ptr(out), _ptr(S),
-                                        None if S is None else C.byref(rms)))
+        fn = self._lib.ens_stack_noalloc if noalloc else self._lib.ens_stack
+        self._check(fn(self._h, C.byref(grid), _ptr(params), _ptr(out), _ptr(S),
+                       None if S is None else C.byref(rms)))
         return out, (None if S is None else rms.value)
 
     # -------------------------------------------------------------- objective

@@ -89,6 +89,8 @@ struct ens_ctx {
     };
     std::map<std::string, Shape> tune_cache;
     std::string device_tag;   // "<arch>/<CUs>": prefix of the keys in the shape file
+    void *scratch = nullptr;  // this device's copy of `scratch` (ens_stack_noalloc)
+    hipError_t scratch_err = hipSuccess;
     hipGraphExec_t graph_exec = nullptr;
     hipGraph_t graph = nullptr;
     void drop_graph()
@@ -130,6 +132,46 @@ ens_status fail(ens_ctx *ctx, ens_status st, const char *fmt, ...)
             return fail(ctx, e_ == hipErrorOutOfMemory ? ENS_E_OOM : ENS_E_HIP, "%s: %s", #expr, \
                         hipGetErrorString(e_));                                                   \
     } while (0)
+
+// ---- memory for the entry point that allocates nothing (ens_stack_noalloc)
+
+// the output-CMP list and the coherence RMS of ens_stack_noalloc
+constexpr int32_t NOALLOC_MAX_CMPS = ENS_NOALLOC_MAX_CMPS;
+constexpr size_t NOALLOC_RMS_BYTES = 256;   // the binary64 RMS, padded to the array's alignment
+constexpr size_t NOALLOC_SCRATCH_BYTES = NOALLOC_RMS_BYTES + sizeof(int32_t) * NOALLOC_MAX_CMPS;
+
+}  // namespace
+
+// One copy per device, held until the process ends; host code reaches it only
+// through the address hipGetSymbolAddress returns on that device.
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mutex;
+void *scratch_ptr[MAX_DEVICES] = {};
+
+// The device address of `scratch` on the current device, looked up once per
+// device (with that device current); nullptr with the HIP error in *err.
+void *scratch_address(hipError_t *err)
+{
+    int dev = 0;
+    *err = hipGetDevice(&dev);
+    if (*err != hipSuccess) return nullptr;
+    if (dev < 0 || dev >= MAX_DEVICES) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(scratch_mutex);
+    if (!scratch_ptr[dev]) {
+        void *p = nullptr;
+        *err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (*err != hipSuccess) return nullptr;
+        scratch_ptr[dev] = p;
+    }
+    return scratch_ptr[dev];
+}
 
 int32_t lerp_round(int32_t lo, int32_t hi, int32_t n0, int32_t nt)
 {
@@ -189,6 +231,9 @@ bool finite(float x) { return std::isfinite(x); }
 
 // Device-side range check of candidate indices (they live in device memory).
 ens_status check_candidates(ens_ctx *ctx, const ens_candidates *cands);
+
+// out[i] = i for i < n (the identity output-CMP list)
+hipError_t launch_iota(int32_t *out, int32_t n, hipStream_t s);
 
 // Measured launch shapes persist in a text file shared by the processes that
 // load the library: one line "<device>/<key> <slices> <item order> <dense>"
@@ -263,6 +308,7 @@ ens_status ens_ctx_create(ens_ctx **out, void *stream)
         c->device_tag = arch + "/" + std::to_string(prop.multiProcessorCount);
         load_tune_file(c);
     }
+    c->scratch = scratch_address(&c->scratch_err);
     *out = c;
     return ENS_OK;
 }
@@ -1011,6 +1057,53 @@ ens_status ens_stack(ens_ctx *ctx, const ens_t0_grid *grid, const float *params,
     return ENS_OK;
 }
 
+ens_status ens_stack_noalloc(ens_ctx *ctx, const ens_t0_grid *grid, const float *params, float *stack_out,
+                             const float *S, double *coherence_rms)
+{
+    if (!ctx) return ENS_E_INVALID;
+    if (!ctx->bound) return fail(ctx, ENS_E_STATE, "ens_stack_noalloc: call ens_bind first");
+    if (!grid || !params || !stack_out) return fail(ctx, ENS_E_INVALID, "ens_stack_noalloc: null argument");
+    if (grid->struct_size < sizeof(ens_t0_grid))
+        return fail(ctx, ENS_E_INVALID, "ens_stack_noalloc: struct_size too small");
+    if ((S == nullptr) != (coherence_rms == nullptr))
+        return fail(ctx, ENS_E_INVALID, "ens_stack_noalloc: S and coherence_rms go together");
+    const int32_t n_out = grid->cmp_out ? grid->n_cmp_out : ctx->n_cmp;
+    if (n_out < 1) return fail(ctx, ENS_E_INVALID, "ens_stack_noalloc: no output CMPs");
+    if (n_out > NOALLOC_MAX_CMPS)
+        return fail(ctx, ENS_E_RANGE, "ens_stack_noalloc: at most %d output CMPs (got %d); use ens_stack",
+                    NOALLOC_MAX_CMPS, n_out);
+    if (grid->cmp_out)
+        for (int32_t o = 0; o < n_out; ++o)
+            if (grid->cmp_out[o] < 0 || grid->cmp_out[o] >= ctx->n_cmp)
+                return fail(ctx, ENS_E_RANGE, "ens_stack_noalloc: cmp_out[%d] = %d out of range", o,
+                            grid->cmp_out[o]);
+    if (grid->t_begin < 0 || grid->t_end > ctx->nt || grid->t_begin >= grid->t_end)
+        return fail(ctx, ENS_E_RANGE, "ens_stack_noalloc: need 0 <= t_begin < t_end <= nt");
+    if (!ctx->scratch)
+        return fail(ctx, ENS_E_HIP, "ens_stack_noalloc: no device address for the scratch array: %s",
+                    hipGetErrorString(ctx->scratch_err));
+    const int32_t n_t = grid->t_end - grid->t_begin;
+    hipStream_t st = ctx->stream;
+    unsigned char *base = static_cast<unsigned char *>(ctx->scratch);
+    double *rms_dev = reinterpret_cast<double *>(base);
+    int32_t *cmp_dev = reinterpret_cast<int32_t *>(base + NOALLOC_RMS_BYTES);
+    // the whole list is written before the stack reads it; nothing carries over between calls
+    if (grid->cmp_out)
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(cmp_dev, grid->cmp_out, sizeof(int32_t) * n_out, hipMemcpyHostToDevice, st));
+    else
+        HIP_OR_FAIL(ctx, launch_iota(cmp_dev, n_out, st));
+    HIP_OR_FAIL(ctx, ens::launch_stack(ctx->op, view_of(ctx, true), cmp_dev, n_out, grid->t_begin, n_t, params,
+                                       stack_out, st));
+    if (S) {
+        HIP_OR_FAIL(ctx, ens::launch_rms(S, static_cast<int64_t>(n_out) * n_t, rms_dev, st));
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(coherence_rms, rms_dev, sizeof(double), hipMemcpyDeviceToHost, st));
+    }
+    // the caller's host list and the returned RMS are settled before returning
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(st));
+    ctx->err.clear();
+    return ENS_OK;
+}
+
 ens_status ens_philox(ens_ctx *ctx, int64_t n, const uint64_t *counters, const uint64_t *key, uint64_t *out)
 {
     if (!ctx) return ENS_E_INVALID;
@@ -1053,6 +1146,18 @@ ens_status ens_jade_draws(ens_ctx *ctx, int64_t n, const uint64_t *words, double
 // ---------------------------------------------------------------------------
 
 namespace {
+
+__global__ void k_iota(int32_t *__restrict__ out, int32_t n)
+{
+    const int32_t i = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n) out[i] = i;
+}
+
+hipError_t launch_iota(int32_t *out, int32_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_iota, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, out, n);
+    return hipGetLastError();
+}
 
 __global__ void k_check_candidates(int64_t n, const int32_t *__restrict__ cmp, const int32_t *__restrict__ t,
                                    int32_t n_cmp, int32_t nt, int32_t *__restrict__ flag)
