@@ -206,10 +206,14 @@ typedef struct {
 /* Search-kernel launch shape.  Zero fields are chosen by measurement: the
  * first search of a given shape times its first launch of each kernel kind,
  * first for every slice count (1, 2, 4, 8) at the first free item order and
- * register budget, then for the other orders and budgets at the fastest count
- * (a launch under 5 ms timed three times, the fastest counting), and keeps the
- * fastest for later searches of that shape on the same context (the
- * generation count does not enter the shape). */
+ * register budget, then for the other orders and budgets at the fastest count,
+ * then (exploration, where offered) packed workgroups of 2, 4 and 8 waves at
+ * the best order and budget so far and the other orders and budgets at the
+ * fastest width (a launch under 5 ms timed three times, the fastest counting),
+ * and keeps the fastest for later searches of that shape (the generation
+ * count does not enter the shape).  Measured shapes persist in a text file:
+ * ENS_TUNE_CACHE if set ("off": none), else ens_tune_cache.txt beside the
+ * library, keyed by device (architecture and compute units) and shape. */
 typedef struct {
     uint32_t struct_size;
     int32_t waves_per_sample_group;  /* trace slices per population (1, 2, 4, 8); 0: measure */
@@ -220,6 +224,19 @@ typedef struct {
                                         3: XCD-contiguous shares, costliest first in each */
     int32_t occupancy;               /* 0: measure; 1: registers as compiled (4 waves per SIMD);
                                         2: held to 64 registers (8 waves per SIMD) */
+    int32_t packing;                 /* exploration launches with fixed F and CR (plain search,
+                                        ENS stage 0): 2, 4 or 8 lays the populations of
+                                        consecutive samples end to end over that many waves
+                                        (one evaluation per lane, no trace slices;
+                                        waves_per_sample_group then applies to the
+                                        exploitation launches only); 1: one population per
+                                        lane group; 0: measured with the other fields where
+                                        under 90% of the lanes would carry a member (when
+                                        waves_per_sample_group and item_order are 0 too),
+                                        else 1.  A packed launch gives the results of one
+                                        population per lane group with one slice, bit for
+                                        bit; slice counts above 1 change the order of the
+                                        window sums. */
 } ens_tuning;
 
 /* Work and device time of the last ens_search, per kernel kind:
@@ -239,6 +256,7 @@ typedef struct {
     int32_t order_used[2];   /* item order chosen (1 or 2) for kinds [0] and [1] */
     int32_t dense_used[2];   /* 1 if the 64-register variant was chosen */
     double tune_ms;          /* device time spent measuring launch shapes in this call */
+    int32_t packed_used;     /* waves of a packed exploration workgroup, 0 if not packed */
 } ens_stats;
 
 /* ---- context ----------------------------------------------------------- */

@@ -69,7 +69,7 @@ struct ens_ctx {
     float h16_kq = 0.f;
     uint32_t h16_bbits = 0, h16_shift = 0;
     // search workspace
-    DevBuf lo_tab, hi_tab, items, X, XS, Y, YS, counters, cmp_out, flag, progress;
+    DevBuf lo_tab, hi_tab, items, X, XS, Y, YS, counters, cmp_out, flag, progress, np_tab;
     // statistics of the last search, launch timing events
     ens_stats stats{};
     std::vector<hipEvent_t> events;
@@ -86,6 +86,7 @@ struct ens_ctx {
     // measured launch shapes: key -> (slices, item order)
     struct Shape {
         int nsl, order, dense;
+        int packed;           // waves of a packed workgroup, 0 when not packed, -1 not measured
     };
     std::map<std::string, Shape> tune_cache;
     std::string device_tag;   // "<arch>/<CUs>": prefix of the keys in the shape file
@@ -106,7 +107,7 @@ struct ens_ctx {
         drop_graph();
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
         for (DevBuf *b : {&store, &master, &scale, &meta, &cmp_ptr, &ap_tab, &qexp, &wsc16, &lo_tab, &hi_tab, &items,
-                          &X, &XS, &Y, &YS, &counters, &cmp_out, &flag, &progress})
+                          &X, &XS, &Y, &YS, &counters, &cmp_out, &flag, &progress, &np_tab})
             b->release();
     }
 };
@@ -173,6 +174,9 @@ void *scratch_address(hipError_t *err)
     return scratch_ptr[dev];
 }
 
+// generations per launch-shape trial (the search itself runs all of them)
+constexpr int32_t TUNE_GENERATIONS = 8;
+
 int32_t lerp_round(int32_t lo, int32_t hi, int32_t n0, int32_t nt)
 {
     if (nt <= 1) return lo;
@@ -236,9 +240,9 @@ ens_status check_candidates(ens_ctx *ctx, const ens_candidates *cands);
 hipError_t launch_iota(int32_t *out, int32_t n, hipStream_t s);
 
 // Measured launch shapes persist in a text file shared by the processes that
-// load the library: one line "<device>/<key> <slices> <item order> <dense>"
-// per shape.  The file is ENS_TUNE_CACHE if that is set ("off": none), else
-// ens_tune_cache.txt beside the library.  Lines are appended as shapes are
+// load the library: one line "<device>/<key> <slices> <item order> <dense>
+// <packed waves>" per shape.  The file is ENS_TUNE_CACHE if that is set
+// ("off": none), else ens_tune_cache.txt beside the library.  Lines are appended as shapes are
 // measured; a later line for the same key wins.  Unreadable or unwritable
 // files are ignored: the shapes are then measured again.
 std::mutex tune_file_mutex;
@@ -267,6 +271,9 @@ void load_tune_file(ens_ctx *ctx)
         std::string key;
         ens_ctx::Shape sh{};
         if (!(ls >> key >> sh.nsl >> sh.order >> sh.dense)) continue;
+        // a line without the packed column predates packing: not measured (-1)
+        if (!(ls >> sh.packed)) sh.packed = -1;
+        if (!(sh.packed == -1 || sh.packed == 0 || sh.packed == 2 || sh.packed == 4 || sh.packed == 8)) continue;
         if (key.compare(0, prefix.size(), prefix) != 0) continue;
         if (!(sh.nsl == 1 || sh.nsl == 2 || sh.nsl == 4 || sh.nsl == 8) || sh.order < 1 || sh.order > 3 ||
             sh.dense < 0 || sh.dense > 1)
@@ -281,7 +288,9 @@ void save_tune_entry(const ens_ctx *ctx, const std::string &key, const ens_ctx::
     if (path.empty()) return;
     std::lock_guard<std::mutex> lock(tune_file_mutex);
     std::ofstream out(path, std::ios::app);
-    if (out) out << ctx->device_tag << "/" << key << " " << sh.nsl << " " << sh.order << " " << sh.dense << "\n";
+    if (out)
+        out << ctx->device_tag << "/" << key << " " << sh.nsl << " " << sh.order << " " << sh.dense << " "
+            << sh.packed << "\n";
 }
 
 }  // namespace
@@ -330,6 +339,9 @@ ens_status ens_set_tuning(ens_ctx *ctx, const ens_tuning *t)
         return fail(ctx, ENS_E_RANGE, "item_order must be 0, 1, 2 or 3 (got %d)", t->item_order);
     if (t->occupancy < 0 || t->occupancy > 2)
         return fail(ctx, ENS_E_RANGE, "occupancy must be 0, 1 or 2 (got %d)", t->occupancy);
+    const int pk = t->packing;
+    if (!(pk == 0 || pk == 1 || pk == 2 || pk == 4 || pk == 8))
+        return fail(ctx, ENS_E_RANGE, "packing must be 0, 1, 2, 4 or 8 (got %d)", pk);
     ctx->tuning = *t;
     ctx->err.clear();
     return ENS_OK;
@@ -580,25 +592,28 @@ ens_status ens_search_bound(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bou
             }
         }
     };
-    auto costliest_first = [&](const std::vector<int4> &items) {
+    // an item's cost: the lanes it evaluates (ns NP, or for a packed item the
+    // lanes in .w) times the traces of its widest aperture
+    auto costliest_first = [&](const std::vector<int4> &items, bool packed_items_) {
         std::vector<int4> v = items;
         auto cost = [&](const int4 &it) {
             const int32_t ns = it.z & 0xff, st = it.z >> 8;
             const int32_t tm = it.y + (ns - 1) * st;
             const int32_t ap = lerp_round(ctx->ap_lo, ctx->ap_hi, tm, nt);
-            return static_cast<double>(ns) * it.w * (2 * ap + 1) * traces_per_cmp;
+            const double lanes = packed_items_ ? it.w : static_cast<double>(ns) * it.w;
+            return lanes * (2 * ap + 1) * traces_per_cmp;
         };
         std::stable_sort(v.begin(), v.end(), [&](const int4 &x, const int4 &y) { return cost(x) > cost(y); });
         return v;
     };
     // the share of XCD x under the block remapping of the kernels (xcd_remap)
-    auto xcd_costliest_first = [&](const std::vector<int4> &items) {
+    auto xcd_costliest_first = [&](const std::vector<int4> &items, bool packed_items_) {
         std::vector<int4> v = items;
         const size_t n = v.size(), per = n / 8, rem = n % 8;
         for (size_t x = 0; x < 8; ++x) {
             const size_t b = x * per + std::min(x, rem), e = b + per + (x < rem ? 1 : 0);
             std::vector<int4> part(v.begin() + b, v.begin() + e);
-            part = costliest_first(part);
+            part = costliest_first(part, packed_items_);
             std::copy(part.begin(), part.end(), v.begin() + b);
         }
         return v;
@@ -613,19 +628,63 @@ ens_status ens_search_bound(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bou
     }
     size_t item_off[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}}, n_items_total = 0;
     for (int c = 0; c < 3; ++c) {
-        cls_items[c][2] = costliest_first(cls_items[c][1]);
-        cls_items[c][3] = xcd_costliest_first(cls_items[c][1]);
+        cls_items[c][2] = costliest_first(cls_items[c][1], false);
+        cls_items[c][3] = xcd_costliest_first(cls_items[c][1], false);
         for (int od = 1; od <= 3; ++od) {
             item_off[c][od] = n_items_total;
             n_items_total += cls_items[c][od].size();
         }
     }
+    // packed exploration (fixed F and CR): consecutive estimated t of a group
+    // laid end to end over the 64 G lanes of G waves
+    // Packing is measured only where one population per lane group leaves
+    // lanes idle: under 90% of the exploration items' lanes carrying a member
+    // (populations of 33..63 members fill a wave only once).
+    double lanes_busy = 0.0;
+    for (const int4 &it : cls_items[0][1]) lanes_busy += static_cast<double>(it.z & 0xff) * it.w;
+    const bool can_pack = !de->adapt;
+    const bool measure_pack =
+        can_pack && lanes_busy < 0.9 * static_cast<double>(ens::WAVE) * static_cast<double>(cls_items[0][1].size());
+    constexpr int N_PACK = 3;
+    const int32_t pack_waves[N_PACK] = {2, 4, 8};
+    std::vector<int4> packed_items[N_PACK][4];   // [waves][order 1, 2, 3 at index 1, 2, 3]
+    size_t packed_off[N_PACK][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+    auto pack_index = [&](int waves) { return waves == 2 ? 0 : (waves == 4 ? 1 : 2); };
+    if (can_pack) {
+        for (int pi = 0; pi < N_PACK; ++pi) {
+            const int32_t G = pack_waves[pi], lanes = ens::WAVE * G;
+            const int32_t max_ns = std::min(255, ens::PACK_MAX_SAMPLES_PER_WAVE * G);
+            for (int32_t gidx = 0; gidx < (ens ? n_buckets : n_out); ++gidx) {
+                int32_t t = t_begin + init_of[0];
+                while (t < grid->t_end) {
+                    int32_t ns = 0, used = 0;
+                    while (ns < max_ns && t + ns * stride < grid->t_end) {
+                        const int32_t np = lerp_round(de->np_lo, de->np_hi, t + ns * stride, nt);
+                        if (used + np > lanes) break;
+                        used += np;
+                        ++ns;
+                    }
+                    packed_items[pi][1].push_back(make_int4(gidx, t, ns | (stride << 8), used));
+                    t += ns * stride;
+                }
+            }
+            packed_items[pi][2] = costliest_first(packed_items[pi][1], true);
+            packed_items[pi][3] = xcd_costliest_first(packed_items[pi][1], true);
+            for (int od = 1; od <= 3; ++od) {
+                packed_off[pi][od] = n_items_total;
+                n_items_total += packed_items[pi][od].size();
+            }
+        }
+    }
+    std::vector<int32_t> np_tab(static_cast<size_t>(nt));
+    for (int32_t n0 = 0; n0 < nt; ++n0) np_tab[n0] = lerp_round(de->np_lo, de->np_hi, n0, nt);
     const size_t pbytes = sizeof(float) * static_cast<size_t>(n_s) * P, sbytes = sizeof(float) * n_s;
     HIP_OR_FAIL(ctx, ctx->lo_tab.ensure(lo.size() * sizeof(float)));
     HIP_OR_FAIL(ctx, ctx->hi_tab.ensure(hi.size() * sizeof(float)));
     HIP_OR_FAIL(ctx, ctx->cmp_out.ensure(cmp_out.size() * sizeof(int32_t)));
     HIP_OR_FAIL(ctx, ctx->items.ensure(std::max<size_t>(n_items_total, 1) * sizeof(int4)));
     HIP_OR_FAIL(ctx, ctx->counters.ensure(8 * sizeof(unsigned long long)));
+    HIP_OR_FAIL(ctx, ctx->np_tab.ensure(np_tab.size() * sizeof(int32_t)));
     if (ens) {
         HIP_OR_FAIL(ctx, ctx->X.ensure(pbytes));
         HIP_OR_FAIL(ctx, ctx->Y.ensure(pbytes));
@@ -642,6 +701,14 @@ ens_status ens_search_bound(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bou
             if (!cls_items[c][od].empty())
                 HIP_OR_FAIL(ctx, hipMemcpyAsync(dev_items + item_off[c][od], cls_items[c][od].data(),
                                                 cls_items[c][od].size() * sizeof(int4), hipMemcpyHostToDevice, st));
+    for (int pi = 0; pi < N_PACK; ++pi)
+        for (int od = 1; od <= 3; ++od)
+            if (!packed_items[pi][od].empty())
+                HIP_OR_FAIL(ctx, hipMemcpyAsync(dev_items + packed_off[pi][od], packed_items[pi][od].data(),
+                                                packed_items[pi][od].size() * sizeof(int4), hipMemcpyHostToDevice,
+                                                st));
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->np_tab.p, np_tab.data(), np_tab.size() * sizeof(int32_t),
+                                    hipMemcpyHostToDevice, st));
 
     float *final_params = nullptr, *final_S = nullptr;
     ens::SearchArgs a{};
@@ -660,6 +727,8 @@ ens_status ens_search_bound(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bou
     a.adapt = de->adapt;
     a.cr_thr = static_cast<uint64_t>(std::ceil(static_cast<double>(de->CR) * 4294967296.0));
     a.counters = ctx->counters.as<unsigned long long>();
+    a.np_tab = ctx->np_tab.as<int32_t>();
+    a.packed = 0;
 
     // launch sequence of the evolution (slices and item order filled in below)
     std::vector<ens_ctx::Launch> seq;
@@ -762,22 +831,41 @@ ens_status ens_search_bound(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bou
                  de->np_lo, de->np_hi, de->adapt, first->n_blocks, n_out, n_t, ctx->ap_hi, stride);
         int nsl = ctx->tuning.waves_per_sample_group, order = ctx->tuning.item_order;
         int dense = ctx->tuning.occupancy == 0 ? -1 : (ctx->tuning.occupancy == 2 ? 1 : 0);
-        if (nsl == 0 || order == 0 || dense < 0) {
+        // packed waves: 0 not packed, -1 to be measured; packing is measured
+        // only when the slice count and item order are too
+        int packed = 0;
+        if (kind == 0 && can_pack) {
+            const int tp = ctx->tuning.packing;
+            packed = tp >= 2 ? tp : (tp == 0 && measure_pack && nsl == 0 && order == 0 ? -1 : 0);
+        }
+        if (packed > 0) nsl = packed;
+        if (nsl == 0 || order == 0 || dense < 0 || packed < 0) {
             auto hit = ctx->tune_cache.find(key);
             if (hit != ctx->tune_cache.end()) {
+                if (packed < 0) {
+                    packed = hit->second.packed;
+                    if (packed > 0) nsl = packed;
+                }
                 if (nsl == 0) nsl = hit->second.nsl;
                 if (order == 0) order = hit->second.order;
                 if (dense < 0) dense = hit->second.dense;
             }
         }
-        if (nsl == 0 || order == 0 || dense < 0) {
+        if (nsl == 0 || order == 0 || dense < 0 || packed < 0) {
             // time the first launch of this kind: every free slice count at the
             // first order and register budget, then the other orders and
-            // budgets at the fastest count
-            const int fixed_nsl = nsl, fixed_order = order, fixed_dense = dense;
+            // budgets at the fastest count; then (where offered) each packed
+            // width at the best order and budget so far, and the other orders
+            // and budgets at the fastest width
+            const int fixed_nsl = packed > 0 ? 0 : nsl, fixed_order = order, fixed_dense = dense,
+                      fixed_packed = packed;
             const int od0 = fixed_order ? fixed_order : 1, dn0 = fixed_dense >= 0 ? fixed_dense : 0;
             const int max_dense = de->adapt ? 0 : 1;  // JADE: one register budget
             ens::SearchArgs ta = first->a;
+            // every generation repeats the same trace loop, so the trials run at
+            // most TUNE_GENERATIONS of them (all trace steps of the launch:
+            // cutting those changed the ranking)
+            ta.ng = std::min(ta.ng, TUNE_GENERATIONS);
             if (kind == 1) {
                 HIP_OR_FAIL(ctx, hipMemsetAsync(ctx->X.p, 0, pbytes, st));
                 HIP_OR_FAIL(ctx, hipMemsetAsync(ctx->XS.p, 0, sbytes, st));
@@ -797,12 +885,28 @@ ens_status ens_search_bound(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bou
                 ta.items = dev_items + item_off[first->item_class][1];
                 HIP_OR_FAIL(ctx, ens::launch_search(P, ctx->store_dtype, ctx->window, kind, warm, ta,
                                                     first->n_blocks, st));
+                if (fixed_packed != 0) {
+                    const int pi = pack_index(fixed_packed > 0 ? fixed_packed : 2);
+                    ens::SearchArgs pa = ta;
+                    pa.packed = 1;
+                    pa.nsl = pack_waves[pi];
+                    pa.items = dev_items + packed_off[pi][1];
+                    if (pa.progress)
+                        HIP_OR_FAIL(ctx, hipMemsetAsync(pa.progress, 0, sizeof(unsigned long long), st));
+                    HIP_OR_FAIL(ctx, ens::launch_search(P, ctx->store_dtype, ctx->window, kind, warm, pa,
+                                                        static_cast<int32_t>(packed_items[pi][1].size()), st));
+                }
             }
             float best = -1.f;
-            auto trial = [&](int ns, int od, int dn) -> hipError_t {
+            // ns: slices (packed: waves), od: item order, dn: register budget,
+            // pk: 1 for a packed workgroup of ns waves
+            auto trial = [&](int ns, int od, int dn, int pk, float *ms_out) -> hipError_t {
                 ta.nsl = ns;
                 ta.xcd_order = od != 2;
-                ta.items = dev_items + item_off[first->item_class][od];
+                ta.packed = pk;
+                ta.items = pk ? dev_items + packed_off[pack_index(ns)][od] : dev_items + item_off[first->item_class][od];
+                const int32_t nb =
+                    pk ? static_cast<int32_t>(packed_items[pack_index(ns)][od].size()) : first->n_blocks;
                 hipError_t e = hipSuccess;
                 float ms = -1.f;
                 // launches under 5 ms are timed three times (the fastest counts):
@@ -812,8 +916,8 @@ ens_status ens_search_bound(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bou
                         (e = hipMemsetAsync(ta.progress, 0, sizeof(unsigned long long), st)) != hipSuccess)
                         return e;
                     if ((e = hipEventRecord(ctx->events[0], st)) != hipSuccess) return e;
-                    if ((e = ens::launch_search(P, ctx->store_dtype, ctx->window, kind, dn, ta, first->n_blocks,
-                                                st)) != hipSuccess)
+                    if ((e = ens::launch_search(P, ctx->store_dtype, ctx->window, kind, dn, ta, nb, st)) !=
+                        hipSuccess)
                         return e;
                     if ((e = hipEventRecord(ctx->events[1], st)) != hipSuccess) return e;
                     if ((e = hipEventSynchronize(ctx->events[1])) != hipSuccess) return e;
@@ -828,30 +932,66 @@ ens_status ens_search_bound(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bou
                     nsl = ns;
                     order = od;
                     dense = dn;
+                    packed = pk ? ns : 0;
                 }
+                if (ms_out) *ms_out = ms;
                 return hipSuccess;
             };
-            const int nsl_opts[4] = {1, 2, 4, 8};
-            for (int ns : nsl_opts)
-                if (fixed_nsl == 0 || ns == fixed_nsl) HIP_OR_FAIL(ctx, trial(ns, od0, dn0));
-            const int ns_best = nsl;
-            for (int od = 1; od <= 3; ++od)
-                for (int dn = 0; dn <= max_dense; ++dn)
-                    if (!(od == od0 && dn == dn0) && (fixed_order == 0 || od == fixed_order) &&
-                        (fixed_dense < 0 || dn == fixed_dense))
-                        HIP_OR_FAIL(ctx, trial(ns_best, od, dn));
-            ctx->tune_cache[key] = {nsl, order, dense};
+            if (fixed_packed <= 0) {
+                const int nsl_opts[4] = {1, 2, 4, 8};
+                for (int ns : nsl_opts)
+                    if (fixed_nsl == 0 || ns == fixed_nsl) HIP_OR_FAIL(ctx, trial(ns, od0, dn0, 0, nullptr));
+                const int ns_best = nsl;
+                for (int od = 1; od <= 3; ++od)
+                    for (int dn = 0; dn <= max_dense; ++dn)
+                        if (!(od == od0 && dn == dn0) && (fixed_order == 0 || od == fixed_order) &&
+                            (fixed_dense < 0 || dn == fixed_dense))
+                            HIP_OR_FAIL(ctx, trial(ns_best, od, dn, 0, nullptr));
+            }
+            if (fixed_packed != 0) {
+                const int od1 = best < 0.f ? od0 : order, dn1 = best < 0.f ? dn0 : dense;
+                int g_best = fixed_packed;
+                if (fixed_packed < 0) {
+                    float t_best = -1.f;
+                    for (int pi = 0; pi < N_PACK; ++pi) {
+                        float t = -1.f;
+                        HIP_OR_FAIL(ctx, trial(pack_waves[pi], od1, dn1, 1, &t));
+                        if (t_best < 0.f || t < t_best) {
+                            t_best = t;
+                            g_best = pack_waves[pi];
+                        }
+                    }
+                } else {
+                    HIP_OR_FAIL(ctx, trial(g_best, od1, dn1, 1, nullptr));
+                }
+                for (int od = 1; od <= 3; ++od)
+                    for (int dn = 0; dn <= max_dense; ++dn)
+                        if (!(od == od1 && dn == dn1) && (fixed_order == 0 || od == fixed_order) &&
+                            (fixed_dense < 0 || dn == fixed_dense))
+                            HIP_OR_FAIL(ctx, trial(g_best, od, dn, 1, nullptr));
+            }
+            ctx->tune_cache[key] = {nsl, order, dense, packed};
             if (!ctx->device_tag.empty()) save_tune_entry(ctx, key, ctx->tune_cache[key]);
         }
         ctx->stats.waves_used[kind] = nsl;
         ctx->stats.order_used[kind] = order;
         ctx->stats.dense_used[kind] = dense;
+        if (kind == 0) ctx->stats.packed_used = packed;
         for (auto &l : seq)
             if (l.kind == kind && !l.interp) {
                 l.a.nsl = nsl;
-                l.a.xcd_order = order != 2;
-                l.a.items = dev_items + item_off[l.item_class][order];
                 l.dense = dense;
+                if (packed > 0) {
+                    const int pi = pack_index(packed);
+                    l.a.packed = 1;
+                    l.a.xcd_order = order != 2;
+                    l.a.items = dev_items + packed_off[pi][order];
+                    l.n_blocks = static_cast<int32_t>(packed_items[pi][order].size());
+                } else {
+                    l.a.packed = 0;
+                    l.a.xcd_order = order != 2;
+                    l.a.items = dev_items + item_off[l.item_class][order];
+                }
             }
     }
     HIP_OR_FAIL(ctx, hipMemsetAsync(ctx->counters.p, 0, 8 * sizeof(unsigned long long), st));

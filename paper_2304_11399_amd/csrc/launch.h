@@ -56,7 +56,14 @@ struct SearchArgs {
     float *Yp, *YS;           // this stage's state
     unsigned long long *counters;  // [2 KIND] evaluations, [2 KIND + 1] participating traces
     unsigned long long *progress;  // sweep steps finished in this launch (zeroed before it), or null
+    // packed exploration (k_search_packed): populations laid end to end over
+    // the nsl waves of a workgroup; items {group, first t, samples | stride << 8, 0}
+    int32_t packed;
+    const int32_t *np_tab;    // [nt] NP_f per time index
 };
+
+// samples one packed workgroup may hold (populations have at least 4 members)
+constexpr int PACK_MAX_SAMPLES_PER_WAVE = 16;
 
 // Interpolation of the samples a stage skipped (time-sample skipping).
 struct InterpArgs {

@@ -327,6 +327,184 @@ __device__ __forceinline__ void search_body(const SearchArgs &a)
     }
 }
 
+// Exploration (plain search, or ENS stage 0) with fixed F and CR, the
+// populations of consecutive time samples laid end to end over all lanes of
+// the workgroup's nsl waves, so that a population may straddle two waves and
+// no lane idles for want of a whole population (NP_f between 33 and 63 leaves
+// most of a wave empty in the layout above).  Each wave evaluates its own
+// lanes' candidates over every trace of the union aperture, in the order of
+// one slice (the same sums as nsl = 1 there); the members and scores meet in
+// LDS, where each lane finds its population's best (lowest slot among equal
+// scores) and reads the best and its two random members.  The draws, the
+// trial arithmetic and the selection are those of search_body, so the result
+// equals search_body's with one slice bit for bit.
+template <int OP, int DT, int W>
+__device__ __forceinline__ void search_packed_body(const SearchArgs &a)
+{
+    extern __shared__ float lds[];
+    const int32_t nl = WAVE * a.nsl;              // lane slots of the workgroup
+    const int32_t pmax = PACK_MAX_SAMPLES_PER_WAVE * a.nsl;
+    float *lx = lds;                              // [3][nl] members
+    float *ls = lds + 3 * nl;                     // [nl] scores
+    float *lp = lds + 4 * nl;                     // [3][pmax] each sample's best on the previous trace
+    const int32_t L = threadIdx.x;
+    const int32_t lane = L & (WAVE - 1);
+    const int4 it = a.items[a.xcd_order ? xcd_remap(blockIdx.x, gridDim.x) : static_cast<int32_t>(blockIdx.x)];
+    int32_t b0 = 0, nb = 1, k_end = 1, k_begin = 0;
+    if (!a.plain) {
+        b0 = it.x * a.n_bucket;
+        nb = min(a.n_bucket, a.n_out - b0);
+        k_begin = a.k_begin;
+        k_end = min(a.k_end, nb);
+    }
+    const int32_t t_start = it.y, ns = it.z & 0xff, stride = it.z >> 8;
+    // this lane's sample m and slot; lanes past the last population are idle
+    // and stand in as slot 0 of the last one (reads stay inside it, nothing is
+    // written but their own LDS entries)
+    int32_t m = 0, base = 0, np = a.np_tab[t_start];
+    while (m + 1 < ns && L >= base + np) {
+        base += np;
+        m += 1;
+        np = a.np_tab[t_start + m * stride];
+    }
+    const bool live = L < base + np;
+    const int32_t slot = live ? L - base : 0;
+    const int32_t n0 = t_start + m * stride;
+    const int32_t tt = n0 - a.t_begin;
+    const int32_t ap = a.sv.ap_tab[n0];
+    float lo[3] = {0.f, 0.f, 0.f}, hi[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int d = 0; d < OP; ++d) {
+        lo[d] = a.lo_tab[n0 * 3 + d];
+        hi[d] = a.hi_tab[n0 * 3 + d];
+    }
+    const int32_t amax = max(a.sv.ap_tab[t_start], a.sv.ap_tab[t_start + (ns - 1) * stride]);
+    const uint64_t stage = static_cast<uint64_t>(a.stage);
+    uint32_t n_ev = 0;
+    uint64_t sum_m = 0;
+
+    for (int32_t k = k_begin; k < k_end; ++k) {
+        if (a.progress) pace_by_progress(a.progress, k - k_begin);
+        const int32_t o = a.plain ? it.x : b0 + (a.forward ? k : nb - 1 - k);
+        const int32_t prev = k > 0 ? (a.forward ? o - 1 : o + 1) : -1;
+        const int32_t j = __builtin_amdgcn_readfirstlane(a.cmp_out[o]);
+        const int32_t c_lo = max(0, j - amax), c_hi = min(a.sv.n_cmp - 1, j + amax);
+        const uint64_t sid =
+            static_cast<uint64_t>(n0) + static_cast<uint64_t>(a.sv.nt) * static_cast<uint64_t>(j);
+        const int64_t here = static_cast<int64_t>(o) * a.n_t + tt;
+
+        float x[3] = {0.f, 0.f, 0.f};
+        uint64_t w[4];
+        philox4x64_10(sid, stage, 0, static_cast<uint64_t>(slot), a.seed, 0, w);
+#pragma unroll
+        for (int d = 0; d < OP; ++d) x[d] = init_coord(w[d], lo[d], hi[d]);
+        if (!a.plain && a.inject && slot == 0 && prev >= 0) {
+            if (k > k_begin) {
+#pragma unroll
+                for (int d = 0; d < OP; ++d) x[d] = fminf(fmaxf(lp[d * pmax + m], lo[d]), hi[d]);
+            } else {
+                load_clamped<OP>(a.Yp + (static_cast<int64_t>(prev) * a.n_t + tt) * OP, lo, hi, x);
+            }
+        }
+        float S;
+        {
+            const Cand<float> cand = make_cand<OP, float>(x, n0, j, ap, a.sv.nt, a.sv.dt, a.sv.dx);
+            Acc<W, float> acc;
+            acc.reset();
+            accumulate_range<DT, W, float>(a.sv, cand, c_lo, c_hi, 0, 1, acc);
+            S = finish_semblance(acc);
+            if (live) {
+                n_ev += 1;
+                sum_m += static_cast<uint64_t>(acc.M);
+            }
+        }
+        for (int32_t g = 1; g <= a.ng; ++g) {
+            __syncthreads();   // the previous generation's readers are done
+#pragma unroll
+            for (int d = 0; d < OP; ++d) lx[d * nl + L] = x[d];
+            ls[L] = S;
+            __syncthreads();
+            float best = ls[base];
+            int32_t bi = 0;
+            for (int32_t q = 1; q < np; ++q) {
+                const float v = ls[base + q];
+                if (v > best) {
+                    best = v;
+                    bi = q;
+                }
+            }
+            philox4x64_10(sid, stage, static_cast<uint64_t>(g), static_cast<uint64_t>(slot), a.seed, 0, w);
+            const TrialDraw dr = trial_draw(w, slot, np, OP, a.cr_thr, np);
+            float u[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+            for (int d = 0; d < OP; ++d) {
+                const float xb = lx[d * nl + base + bi];
+                const float xr1 = lx[d * nl + base + static_cast<int32_t>(dr.r1)];
+                const float xr2 = lx[d * nl + base + static_cast<int32_t>(dr.r2)];
+                const float v = mutant(x[d], xb, xr1, xr2, a.F, lo[d], hi[d]);
+                u[d] = dr.take[d] ? v : x[d];
+            }
+            const Cand<float> cand = make_cand<OP, float>(u, n0, j, ap, a.sv.nt, a.sv.dt, a.sv.dx);
+            Acc<W, float> acc;
+            acc.reset();
+            accumulate_range<DT, W, float>(a.sv, cand, c_lo, c_hi, 0, 1, acc);
+            const float St = finish_semblance(acc);
+            if (live) {
+                n_ev += 1;
+                sum_m += static_cast<uint64_t>(acc.M);
+            }
+            if (St >= S) {
+#pragma unroll
+                for (int d = 0; d < OP; ++d) x[d] = u[d];
+                S = St;
+            }
+        }
+        // the sample's best: the state of the sample and the seed of its next trace
+        __syncthreads();
+#pragma unroll
+        for (int d = 0; d < OP; ++d) lx[d * nl + L] = x[d];
+        ls[L] = S;
+        __syncthreads();
+        float best = ls[base];
+        int32_t bi = 0;
+        for (int32_t q = 1; q < np; ++q) {
+            const float v = ls[base + q];
+            if (v > best) {
+                best = v;
+                bi = q;
+            }
+        }
+        if (live && slot == bi) {
+#pragma unroll
+            for (int d = 0; d < OP; ++d) {
+                a.Yp[here * OP + d] = x[d];
+                lp[d * pmax + m] = x[d];
+            }
+            a.YS[here] = S;
+        }
+        __syncthreads();   // the seeds are in place before the next trace step reads them
+        if (a.progress && threadIdx.x == 0) atomicAdd(a.progress, 1ull);
+    }
+    const uint64_t tot_ev = wave_sum(static_cast<uint64_t>(n_ev));
+    const uint64_t tot_m = wave_sum(sum_m);
+    if (lane == 0) {
+        atomicAdd(a.counters, static_cast<unsigned long long>(tot_ev));
+        atomicAdd(a.counters + 1, static_cast<unsigned long long>(tot_m));
+    }
+}
+
+template <int OP, int DT, int W>
+__global__ __launch_bounds__(512) void k_search_packed(SearchArgs a)
+{
+    search_packed_body<OP, DT, W>(a);
+}
+
+template <int OP, int DT, int W>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_search_packed_dense(SearchArgs a)
+{
+    search_packed_body<OP, DT, W>(a);
+}
+
 template <int OP, int DT, int W, int KIND>
 __global__ __launch_bounds__(512) void k_search(SearchArgs a)
 {
@@ -351,8 +529,20 @@ hipError_t launch_search_dt(int op, int window, int kind, int dense, const Searc
                            hipStream_t s)
 {
     if (n_blocks == 0) return hipSuccess;
-    const size_t lds = a.nsl > 1 ? sizeof(float) * 2 * a.nsl * (window + 2) * WAVE : 0;
     const dim3 grid(static_cast<unsigned>(n_blocks)), block(WAVE * a.nsl);
+    if (a.packed) {
+        if (a.adapt || kind != 0 || a.stage != 0) return hipErrorInvalidValue;
+        const size_t lds = sizeof(float) * (4 * WAVE + 3 * PACK_MAX_SAMPLES_PER_WAVE) * a.nsl;
+        if (!dense) {
+            ENS_DISPATCH_OP(op, ENS_DISPATCH_W(window,
+                hipLaunchKernelGGL((k_search_packed<OP, DT, W>), grid, block, lds, s, a)));
+        } else {
+            ENS_DISPATCH_OP(op, ENS_DISPATCH_W(window,
+                hipLaunchKernelGGL((k_search_packed_dense<OP, DT, W>), grid, block, lds, s, a)));
+        }
+        return hipGetLastError();
+    }
+    const size_t lds = a.nsl > 1 ? sizeof(float) * 2 * a.nsl * (window + 2) * WAVE : 0;
     if (a.adapt && kind == 0) {
         ENS_DISPATCH_OP(op, ENS_DISPATCH_W(window,
             hipLaunchKernelGGL((k_search_jade<OP, DT, W, 0>), grid, block, lds, s, a)));

@@ -4,6 +4,9 @@ import sys
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+# the tests measure launch shapes afresh and write no shape file; the test of
+# the file names its own
+os.environ["ENS_TUNE_CACHE"] = "off"
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 

@@ -40,8 +40,8 @@ def test_struct_sizes_match_header_layout():
     assert C.sizeof(ens.Traces) == 72
     assert C.sizeof(ens.DeCfg) == 68
     assert C.sizeof(ens.Result) == 56
-    assert C.sizeof(ens.Stats) == 168
-    assert C.sizeof(ens.Tuning) == 24
+    assert C.sizeof(ens.Stats) == 176
+    assert C.sizeof(ens.Tuning) == 28
 
 
 def test_struct_sizes_match_the_c_compiler(tmp_path):
@@ -145,6 +145,10 @@ def test_tuning_and_building_block_validation():
         assert lib.ens_set_tuning(h, C.byref(t)) == 0
         t.use_graph, t.collect_timing = 1, 1
         assert lib.ens_set_tuning(h, C.byref(t)) == -1
+        t.use_graph, t.collect_timing, t.packing = 0, 0, 3
+        assert lib.ens_set_tuning(h, C.byref(t)) == -2
+        t.packing = 8
+        assert lib.ens_set_tuning(h, C.byref(t)) == 0
         st = ens._sized(ens.Stats)
         assert lib.ens_last_stats(h, C.byref(st)) == 0 and st.launches[0] == 0
         assert lib.ens_de_trial(h, 1, 3, 3, 1, 1, 1, 0.5, 0.9, 1, 1, 1) == -2   # np < 4

@@ -129,3 +129,36 @@ def test_reduced_precision_search(ens, store):
     assert err.max() < (2e-3 if store == "f16" else 2e-2)
     assert out["n_evals"] == evals_ens(24 * 300, 0, 0, 5, 1, 1) + sum(
         24 * oracle.pop_size(de, g.nt, tt) * 7 for tt in range(300))
+
+
+def test_launch_shapes_persist_in_the_shape_file(ens, tmp_path, monkeypatch):
+    path = tmp_path / "shapes.txt"
+    monkeypatch.setenv("ENS_TUNE_CACHE", str(path))
+    g, wl = make_workload("crs_uneven", n_cmp=12, nt=240)
+    de = dict(wl["de"], ng_f=3, n_bucket=6)
+    a = _ctx(ens, g, wl)
+    ra = a.search(base_bounds(wl), de, seed=8)
+    assert a.stats()["tune_ms"] > 0
+    lines = path.read_text().split("\n")
+    lines = [ln for ln in lines if ln]
+    assert len(lines) == 2                       # exploration and exploitation
+    for ln in lines:
+        f = ln.split()
+        assert len(f) == 5 and f[0].startswith("gfx950/")
+        assert int(f[1]) in (1, 2, 4, 8) and int(f[2]) in (1, 2, 3) and int(f[3]) in (0, 1)
+        assert int(f[4]) in (0, 2, 4, 8)
+    b = _ctx(ens, g, wl)                         # a new context reads the file
+    rb = b.search(base_bounds(wl), de, seed=8)
+    assert b.stats()["tune_ms"] == 0
+    assert torch.equal(ra["params"], rb["params"]) and torch.equal(ra["S"], rb["S"])
+    # a line without the packed column (an older file) is used for the slices,
+    # order and registers, and packing is measured for it where it is offered
+    path.write_text("\n".join(" ".join(ln.split()[:4]) for ln in lines) + "\n")
+    c = _ctx(ens, g, wl)
+    rc = c.search(base_bounds(wl), de, seed=8)
+    assert torch.equal(ra["params"], rc["params"])
+    # garbage lines are skipped
+    path.write_text("nonsense\n" + "gfx950/256/x 3 3 3 3\n")
+    d = _ctx(ens, g, wl)
+    assert torch.equal(ra["params"], d.search(base_bounds(wl), de, seed=8)["params"])
+    assert d.stats()["tune_ms"] > 0
