@@ -85,6 +85,9 @@ def parse():
                          "3 costliest first within XCD-contiguous shares (0: measure)")
     ap.add_argument("--occupancy", type=int, default=0,
                     help="search kernel registers: 1 as compiled, 2 held to 64 (0: measure)")
+    ap.add_argument("--packing", type=int, default=0,
+                    help="exploration workgroups: 1 one population per lane group, 2/4/8 "
+                         "populations packed over that many waves (0: measure)")
     ap.add_argument("--graph", action="store_true", help="replay the trace steps as a HIP graph")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the equal-accuracy comparison of the variants")
@@ -92,6 +95,9 @@ def parse():
     ap.add_argument("--no-gap", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=8.0,
                     help="CPU work per oracle timing (all cores, then one core)")
+    ap.add_argument("--budget-s", type=float, default=420.0,
+                    help="wall-clock seconds after which the remaining comparison rows are "
+                         "skipped (and listed as skipped)")
     return ap.parse_args()
 
 
@@ -160,16 +166,20 @@ def variants_for(name, wl):
     de0 = dict(wl["de"])
     plain0 = dict(de0, ens_enabled=0, polish_steps=0, n_skip=0)
     if name == "crs_diff":
+        # most telling rows first (a time budget may cut the list short): the
+        # configured budget, the per-sample binary32 search at it, the smaller
+        # ENS budget with and without binary16 storage and polish, then the rest
         nop = dict(de0, polish_steps=0)
+        small = dict(np_lo=16, np_hi=16, ng_f=20)
         return [("ens_f16_polish", "f16", dict(de0)),
-                ("ens_f16_polish", "f16", dict(de0, np_lo=16, np_hi=16, ng_f=20)),
-                ("ens_f16_polish", "f16", dict(de0, np_lo=16, np_hi=16, ng_f=10)),
-                ("ens_f16", "f16", dict(nop)),
-                ("ens_f16", "f16", dict(nop, np_lo=16, np_hi=16, ng_f=20)),
-                ("ens_f32", "f32", dict(nop)),
-                ("ens_f32", "f32", dict(nop, np_lo=16, np_hi=16, ng_f=20)),
-                ("plain_f32", "f32", dict(plain0, np_lo=16, np_hi=16, ng_f=20)),
                 ("plain_f32", "f32", dict(plain0)),
+                ("ens_f16_polish", "f16", dict(de0, **small)),
+                ("ens_f16", "f16", dict(nop, **small)),
+                ("ens_f32", "f32", dict(nop, **small)),
+                ("plain_f32", "f32", dict(plain0, **small)),
+                ("ens_f16_polish", "f16", dict(de0, np_lo=16, np_hi=16, ng_f=10)),
+                ("ens_f32", "f32", dict(nop)),
+                ("ens_f16", "f16", dict(nop)),
                 ("plain_f32", "f32", dict(plain0, ng_f=80))]
     if name == "crs_ens":
         return [("ens", "f32", dict(de0)),
@@ -194,30 +204,44 @@ def variants_for(name, wl):
     return []
 
 
-def compare_equal_accuracy(ctxs, bounds, wl, g, seed, note):
+def compare_equal_accuracy(ctxs, bounds, wl, g, seed, note, main=None, deadline=None):
     """Each row's throughput and gap; the fastest row of each method whose mean
     gap to the reference maxima is <= 1e-3 is that method's throughput at
-    equal accuracy."""
+    equal accuracy.  main = (store, de, seconds, S64) of the timed steps: the
+    row with that configuration takes their mean step time (bind + search +
+    re-score) instead of a run of its own.  Rows not started by `deadline`
+    (time.perf_counter()) are listed as skipped."""
     import torch
-    rows = []
+    rows, skipped = [], []
     variants = variants_for(wl["name"], wl)
     for k, (kind, store, de) in enumerate(variants):
-        c = ctxs[store]
-        for attempt in range(2):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            out = c.search(bounds, de, seed, rescore_fp64=True)
-            torch.cuda.synchronize()
-            sec = time.perf_counter() - t0
-            if c.stats()["tune_ms"] == 0:  # no launch-shape measurement inside the clock
-                break
-        gap = gap_stats(wl["name"], out["S64"].cpu().numpy(), g.nt, g)
-        note(f"compare {k + 1}/{len(variants)} {kind} {de['np_lo']}x{de['ng_f']}: {1e3 * sec:.1f} ms")
+        if main is not None and store == main[0] and de == main[1]:
+            sec, S64 = main[2], main[3]
+            note(f"compare {k + 1}/{len(variants)} {kind} {de['np_lo']}x{de['ng_f']}: "
+                 f"{1e3 * sec:.1f} ms (the timed steps)")
+            n_evals = main[4]
+        elif deadline is not None and time.perf_counter() > deadline:
+            skipped.append({"method": kind, "np": de["np_lo"], "ng": de["ng_f"], "store": store})
+            note(f"compare {k + 1}/{len(variants)} {kind} {de['np_lo']}x{de['ng_f']}: skipped (time)")
+            continue
+        else:
+            c = ctxs[store]
+            for attempt in range(2):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                out = c.search(bounds, de, seed, rescore_fp64=True)
+                torch.cuda.synchronize()
+                sec = time.perf_counter() - t0
+                if c.stats()["tune_ms"] == 0:  # no launch-shape measurement inside the clock
+                    break
+            S64, n_evals = out["S64"].cpu().numpy(), out["n_evals"]
+            note(f"compare {k + 1}/{len(variants)} {kind} {de['np_lo']}x{de['ng_f']}: {1e3 * sec:.1f} ms")
+        gap = gap_stats(wl["name"], S64, g.nt, g)
         rows.append({"method": kind, "np": de["np_lo"], "ng": de["ng_f"],
                      "n_skip": de.get("n_skip", 0), "adapt": de.get("adapt", 0),
                      "store": store, "polish": de.get("polish_steps", 0),
                      "ms": round(1e3 * sec, 2), "zo_samples_per_s": round(g.n_cmp * g.nt / sec, 1),
-                     "evals": out["n_evals"], "gap_mean": gap["mean"] if gap else None,
+                     "evals": n_evals, "gap_mean": gap["mean"] if gap else None,
                      "frac_le_1e-3": gap["frac_le_1e-3"] if gap else None})
     best = {}
     for r in rows:
@@ -230,7 +254,7 @@ def compare_equal_accuracy(ctxs, bounds, wl, g, seed, note):
         if a in best and b in best:
             return round(best[a]["zo_samples_per_s"] / best[b]["zo_samples_per_s"], 3)
         return None
-    res = {"runs": rows, "best_at_gap_le_1e-3": best}
+    res = {"runs": rows, "best_at_gap_le_1e-3": best, "skipped_for_time": skipped}
     if wl["name"] == "crs_diff":
         res["ens_f16_polish_over_plain_f32_zo_samples_per_s"] = ratio("ens_f16_polish", "plain_f32")
         res["ens_f16_over_plain_f32"] = ratio("ens_f16", "plain_f32")
@@ -261,6 +285,7 @@ def gap_stats(name, S64, nt, g):
 
 
 def main():
+    t_start = time.perf_counter()
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         msg = ("the library runs on one GPU: the search shards by bucket across GPUs "
@@ -286,7 +311,7 @@ def main():
     with torch.cuda.stream(stream):
         ctx = ens.Context(stream)
         ctx.set_tuning(waves_per_sample_group=args.waves, use_graph=int(args.graph),
-                       item_order=args.order, occupancy=args.occupancy)
+                       item_order=args.order, occupancy=args.occupancy, packing=args.packing)
         # the one-time host-to-device upload, outside the steps
         torch.cuda.synchronize()
         t_up = time.perf_counter()
@@ -313,8 +338,11 @@ def main():
         bind_ms = 1e3 * (time.perf_counter() - t_b)
         note(f"warm-up done; timing {args.steps} step(s)")
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for k in range(args.steps):
             out = step()
+            # each step ends in a stream synchronisation (the search reads its
+            # counters back), so this line costs the clock a print
+            note(f"step {k + 1}/{args.steps} done")
         torch.cuda.synchronize()
         sec = time.perf_counter() - t0
         ms_step = 1e3 * sec / args.steps
@@ -324,11 +352,11 @@ def main():
 
         # one more step with per-launch event timing, outside the timed region
         ctx.set_tuning(waves_per_sample_group=args.waves, collect_timing=1, item_order=args.order,
-                       occupancy=args.occupancy)
+                       occupancy=args.occupancy, packing=args.packing)
         step()
         st = ctx.stats()
         ctx.set_tuning(waves_per_sample_group=args.waves, item_order=args.order,
-                       occupancy=args.occupancy)
+                       occupancy=args.occupancy, packing=args.packing)
         # quality outputs of the last step, outside the timed region: the
         # zero-offset stack along the winners and the coherence-panel RMS
         torch.cuda.synchronize()
@@ -345,7 +373,9 @@ def main():
                 c.bind(traces, g.cmp_ptr, g.offset, g.dt, g.dx, wl["op"], wl["window"], wl["ap_lo"],
                        wl["ap_hi"], store=s)
                 ctxs[s] = c
-            comparison = compare_equal_accuracy(ctxs, bounds, wl, g, wl["search_seed"], note)
+            comparison = compare_equal_accuracy(
+                ctxs, bounds, wl, g, wl["search_seed"], note,
+                main=(store, de, sec / args.steps, S64, evals), deadline=t_start + args.budget_s)
 
     if wl["de"]["ens_enabled"]:
         expect = ens.evals_ens(P_d, de["np_lo"], de["ng_f"], de["np_bf"], de["ng_bf"],
@@ -363,9 +393,14 @@ def main():
     flops_per_launch = ex["sum_m"] * flops_per_pair(wl["op"], W) / ex["launches"]
     gbs = bytes_per_launch / per_launch_s / 1e9
     tflops = flops_per_launch / per_launch_s / 1e12
-    kname = ("k_search_dense" if ex.get("dense") else "k_search") + \
-        f"<{wl['op']}, {DT_CODE[store]}, {W}, 0>"
-    shape = {"waves": ex.get("waves"), "item_order": ex.get("item_order"), "dense": ex.get("dense")}
+    if ex.get("packed"):
+        kname = ("k_search_packed_dense" if ex.get("dense") else "k_search_packed") + \
+            f"<{wl['op']}, {DT_CODE[store]}, {W}>"
+    else:
+        kname = ("k_search_dense" if ex.get("dense") else "k_search") + \
+            f"<{wl['op']}, {DT_CODE[store]}, {W}, 0>"
+    shape = {"waves": ex.get("waves"), "item_order": ex.get("item_order"), "dense": ex.get("dense"),
+             "packed": ex.get("packed", 0)}
     prof = measured_profile(args.workload, f"void ens::{kname}(ens::SearchArgs)", shape)
     traffic = None if prof is None else round(prof["traffic_bytes_per_launch"])
     roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": FP32_PEAK_TFLOPS,
