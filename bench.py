@@ -417,7 +417,7 @@ def main():
             # HBM (the measured HBM bytes are "traffic"); not an HBM fraction
             "cache_served_gather_gbs": round(gbs, 1)}
     if prof is not None:
-        roof["measured"] = {k: prof[k] for k in ("hbm_gbs", "valu_busy", "ta_busy", "l2_hit",
+        roof["measured"] = {k: prof[k] for k in ("hbm_gbs", "valu_cycles_per_instr", "ta_busy", "l2_hit",
                                                  "profile") if k in prof}
 
     gap = None if args.no_gap else gap_stats(args.workload, S64, g.nt, g)
