@@ -160,7 +160,7 @@ def cpu_baseline(g, wl, de, bounds, seconds):
 
 def variants_for(name, wl):
     """(method, storage, search configuration) rows of the equal-accuracy
-    comparison.  crs_diff: the spec claim, the binary16 search with the
+    comparison.  crs_diff: the binary16 + polish claim, the binary16 search with the
     adjoint polish against the per-sample binary32 search the paper compares
     with, with ENS in binary32 and in binary16 without polish between them."""
     de0 = dict(wl["de"])
