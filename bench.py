@@ -88,6 +88,8 @@ def parse():
     ap.add_argument("--packing", type=int, default=0,
                     help="exploration workgroups: 1 one population per lane group, 2/4/8 "
                          "populations packed over that many waves (0: measure)")
+    ap.add_argument("--gather", type=int, default=0,
+                    help="1: binary32 windows staged per trace in LDS (0: read directly)")
     ap.add_argument("--graph", action="store_true", help="replay the trace steps as a HIP graph")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the equal-accuracy comparison of the variants")
@@ -311,7 +313,7 @@ def main():
     with torch.cuda.stream(stream):
         ctx = ens.Context(stream)
         ctx.set_tuning(waves_per_sample_group=args.waves, use_graph=int(args.graph),
-                       item_order=args.order, occupancy=args.occupancy, packing=args.packing)
+                       item_order=args.order, occupancy=args.occupancy, packing=args.packing, gather=args.gather)
         # the one-time host-to-device upload, outside the steps
         torch.cuda.synchronize()
         t_up = time.perf_counter()
@@ -352,11 +354,11 @@ def main():
 
         # one more step with per-launch event timing, outside the timed region
         ctx.set_tuning(waves_per_sample_group=args.waves, collect_timing=1, item_order=args.order,
-                       occupancy=args.occupancy, packing=args.packing)
+                       occupancy=args.occupancy, packing=args.packing, gather=args.gather)
         step()
         st = ctx.stats()
         ctx.set_tuning(waves_per_sample_group=args.waves, item_order=args.order,
-                       occupancy=args.occupancy, packing=args.packing)
+                       occupancy=args.occupancy, packing=args.packing, gather=args.gather)
         # quality outputs of the last step, outside the timed region: the
         # zero-offset stack along the winners and the coherence-panel RMS
         torch.cuda.synchronize()
@@ -396,6 +398,8 @@ def main():
     if ex.get("packed"):
         kname = ("k_search_packed_dense" if ex.get("dense") else "k_search_packed") + \
             f"<{wl['op']}, {DT_CODE[store]}, {W}>"
+    elif args.gather == 1 and store == "f32" and not de.get("adapt", 0):
+        kname = f"k_search_tiles<{wl['op']}, {W}, 0>"
     else:
         kname = ("k_search_dense" if ex.get("dense") else "k_search") + \
             f"<{wl['op']}, {DT_CODE[store]}, {W}, 0>"

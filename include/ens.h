@@ -237,6 +237,12 @@ typedef struct {
                                         population per lane group with one slice, bit for
                                         bit; slice counts above 1 change the order of the
                                         window sums. */
+    int32_t gather;                  /* 0: windows read directly from the rows; 1: binary32
+                                        rows staged per trace in LDS (the column range every
+                                        window may read, bounded from the samples' boxes) and
+                                        the windows read from LDS, for searches with fixed F
+                                        and CR outside packed workgroups.  Same results bit
+                                        for bit; measured slower on the CRS lines. */
 } ens_tuning;
 
 /* Work and device time of the last ens_search, per kernel kind:

@@ -82,7 +82,7 @@ class Candidates(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("waves_per_sample_group", C.c_int32),
                 ("use_graph", C.c_int32), ("collect_timing", C.c_int32), ("item_order", C.c_int32),
-                ("occupancy", C.c_int32), ("packing", C.c_int32)]
+                ("occupancy", C.c_int32), ("packing", C.c_int32), ("gather", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -195,11 +195,11 @@ class Context:
         return self._lib.ens_last_error(self._h).decode()
 
     def set_tuning(self, waves_per_sample_group=0, use_graph=0, collect_timing=0, item_order=0,
-                   occupancy=0, packing=0):
+                   occupancy=0, packing=0, gather=0):
         """Launch shape of the search kernels; 0 = chosen by measurement."""
         t = _sized(Tuning, waves_per_sample_group=waves_per_sample_group, use_graph=use_graph,
                    collect_timing=collect_timing, item_order=item_order, occupancy=occupancy,
-                   packing=packing)
+                   packing=packing, gather=gather)
         self._check(self._lib.ens_set_tuning(self._h, C.byref(t)))
 
     def stats(self):

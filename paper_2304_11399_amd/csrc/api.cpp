@@ -64,6 +64,7 @@ struct ens_ctx {
     int32_t nt = 0, n_cmp = 0, store_dtype = ENS_DTYPE_F32;
     float dt = 0.f, dx = 0.f;
     int32_t op = 0, window = 0, ap_lo = 0, ap_hi = 0;
+    int32_t max_ap_traces = 0;   // the most traces any output CMP's widest aperture holds
     DevBuf store, master, scale, meta, cmp_ptr, ap_tab, qexp, wsc16;
     // binary16 window constants (StoreView h16_*)
     float h16_kq = 0.f;
@@ -342,6 +343,7 @@ ens_status ens_set_tuning(ens_ctx *ctx, const ens_tuning *t)
     const int pk = t->packing;
     if (!(pk == 0 || pk == 1 || pk == 2 || pk == 4 || pk == 8))
         return fail(ctx, ENS_E_RANGE, "packing must be 0, 1, 2, 4 or 8 (got %d)", pk);
+    if (t->gather < 0 || t->gather > 1) return fail(ctx, ENS_E_RANGE, "gather must be 0 or 1 (got %d)", t->gather);
     ctx->tuning = *t;
     ctx->err.clear();
     return ENS_OK;
@@ -485,6 +487,15 @@ ens_status ens_bind(ens_ctx *ctx, const ens_traces *tr, const ens_geometry *g, c
     ctx->window = sem->window;
     ctx->ap_lo = sem->ap_lo;
     ctx->ap_hi = sem->ap_hi;
+    {
+        const int32_t apm = std::max(sem->ap_lo, sem->ap_hi);
+        int64_t most = 0;
+        for (int32_t j = 0; j < g->n_cmp; ++j) {
+            const int32_t lo = std::max(0, j - apm), hi = std::min(g->n_cmp - 1, j + apm);
+            most = std::max<int64_t>(most, g->cmp_ptr[hi + 1] - g->cmp_ptr[lo]);
+        }
+        ctx->max_ap_traces = static_cast<int32_t>(most);
+    }
     ctx->bound = true;
     ctx->err.clear();
     return ENS_OK;
@@ -729,6 +740,11 @@ ens_status ens_search_bound(ens_ctx *ctx, const ens_t0_grid *grid, const ens_bou
     a.counters = ctx->counters.as<unsigned long long>();
     a.np_tab = ctx->np_tab.as<int32_t>();
     a.packed = 0;
+    // LDS-staged binary32 windows (ens_tuning.gather = 1; fixed F and CR, one
+    // population per lane group), where the table fits
+    a.tiles = ctx->tuning.gather == 1 && ctx->store_dtype == ENS_DTYPE_F32 && !de->adapt &&
+              static_cast<size_t>(ctx->max_ap_traces) * 8 <= 64 * 1024;
+    a.tile_cap = ctx->max_ap_traces;
 
     // launch sequence of the evolution (slices and item order filled in below)
     std::vector<ens_ctx::Launch> seq;

@@ -126,6 +126,63 @@ __device__ __forceinline__ void accumulate_cmps(const StoreView &sv, const Cand<
     }
 }
 
+// Binary32 windows through LDS: tab[i - i0] = {first column, columns} of the
+// range every window of trace i may read for the workgroup's candidates
+// (columns < 0: read directly); stage: this wave's 2 x (TILE_STAGE_MAX + 8)
+// floats; zero8: 8 zero floats.  The staged samples and the arithmetic are
+// those of accum_trace, so the sums are bit for bit those of the direct path.
+template <int W>
+__device__ __forceinline__ void accumulate_cmps_tiles(const StoreView &sv, const Cand<float> &cand, int32_t c_lo,
+                                                      int32_t c_hi, int32_t first, int32_t step,
+                                                      Acc<W, float> &acc, const int2 *tab, int32_t i0,
+                                                      float *stage, const float *zero8, int32_t lane)
+{
+    const float *store = static_cast<const float *>(sv.store);
+    const ENS_CONST_AS int64_t *cmp_ptr = const_view(sv.cmp_ptr);
+    const ENS_CONST_AS TraceMeta *meta = const_view(sv.meta);
+    const float dx = sv.dx;
+    const uint32_t row_bytes = static_cast<uint32_t>(sv.ld * static_cast<int64_t>(sizeof(float)));
+    auto one = [&](const CmpTerm<float> &ct, int32_t i, float *buf) {
+        const float *row = store + static_cast<size_t>(i) * sv.ld;
+        const int2 te = tab[i - i0];
+        const int32_t b = __builtin_amdgcn_readfirstlane(te.x), len = __builtin_amdgcn_readfirstlane(te.y);
+        if (len < 0) {
+            accum_trace<DT_F32, W, false>(acc, cand, ct, meta[i].h2, row, 0u, row_bytes, 1.0f);
+            return;
+        }
+        const __amdgpu_buffer_rsrc_t rs = row_buffer(row, row_bytes);
+#pragma unroll
+        for (int r = 0; r < TILE_STAGE_MAX; r += WAVE)
+            if (r < len) buf[r + lane] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+                                             rs, static_cast<uint32_t>(b + r + lane) * 4u, 0, 0));
+        __builtin_amdgcn_wave_barrier();
+        const TT<float> tt = traveltime<W, 4>(cand, ct, meta[i].h2);
+        acc.M += tt.ok ? 1 : 0;
+        // tt.off is 4 * column for a participating trace
+        const float *src = tt.ok ? buf + (static_cast<int32_t>(tt.off >> 2) - b) : zero8;
+        float u[W + 1];
+#pragma unroll
+        for (int k = 0; k <= W; ++k) u[k] = src[k];
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            const float a = fmadd(tt.f, u[k + 1] - u[k], u[k]);
+            acc.s[k] += a;
+            acc.E = fmadd(a, a, acc.E);
+        }
+        __builtin_amdgcn_wave_barrier();
+    };
+    for (int32_t c = c_lo; c <= c_hi; ++c) {
+        const CmpTerm<float> ct = cmp_term(cand, c, dx);
+        const int32_t i1 = static_cast<int32_t>(cmp_ptr[c + 1]);
+        int32_t i = static_cast<int32_t>(cmp_ptr[c]) + first;
+        for (; i + step < i1; i += 2 * step) {
+            one(ct, i, stage);
+            one(ct, i + step, stage + TILE_STAGE_MAX + 8);
+        }
+        if (i < i1) one(ct, i, stage);
+    }
+}
+
 template <int DT, int W, typename R, bool EXACT = false>
 __device__ __forceinline__ void accumulate_range(const StoreView &sv, const Cand<R> &cand, int32_t c_lo,
                                                  int32_t c_hi, int32_t first, int32_t step,

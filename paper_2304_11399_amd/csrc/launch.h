@@ -60,7 +60,15 @@ struct SearchArgs {
     // the nsl waves of a workgroup; items {group, first t, samples | stride << 8, 0}
     int32_t packed;
     const int32_t *np_tab;    // [nt] NP_f per time index
+    // LDS-staged windows (binary32 rows): per trace step a table of each
+    // aperture trace's column range over the workgroup's boxes, then per trace
+    // the range staged by coalesced loads and the windows read from LDS
+    int32_t tiles;
+    int32_t tile_cap;         // table entries: the most traces any aperture union holds
 };
+
+// binary32 samples one staged trace may span (longer ranges read directly)
+constexpr int TILE_STAGE_MAX = 192;
 
 // samples one packed workgroup may hold (populations have at least 4 members)
 constexpr int PACK_MAX_SAMPLES_PER_WAVE = 16;

@@ -115,14 +115,25 @@ __device__ __forceinline__ void load_clamped(const float *__restrict__ src, cons
 // workgroup's nsl waves (in every CMP, wave w takes the CMP's traces w,
 // w + nsl, w + 2 nsl, ...);
 // partial sums meet in LDS and every wave adds them in the same order.
-template <int DT, int W>
+// The LDS-staged windows of a workgroup (search_body with TILES).
+struct TileCtx {
+    const int2 *tab;      // the step's table of staged column ranges
+    int32_t i0;           // first trace of the table
+    float *stage;         // this wave's two staging buffers
+    const float *zero8;
+};
+
+template <int DT, int W, bool TILES = false>
 __device__ __forceinline__ float eval_slices(const StoreView &sv, const Cand<float> &cand, int32_t c_lo,
                                              int32_t c_hi, int32_t wave, int32_t nsl, int32_t lane,
-                                             float *lds, int &buf, int32_t &M)
+                                             float *lds, int &buf, int32_t &M, const TileCtx &tc)
 {
     Acc<W, float> acc;
     acc.reset();
-    accumulate_range<DT, W, float>(sv, cand, c_lo, c_hi, wave, nsl, acc);
+    if constexpr (TILES)
+        accumulate_cmps_tiles<W>(sv, cand, c_lo, c_hi, wave, nsl, acc, tc.tab, tc.i0, tc.stage, tc.zero8, lane);
+    else
+        accumulate_range<DT, W, float>(sv, cand, c_lo, c_hi, wave, nsl, acc);
     if (nsl > 1) {
         float *mine = lds + ((buf * nsl + wave) * (W + 2)) * WAVE + lane;
 #pragma unroll
@@ -168,6 +179,58 @@ __device__ __forceinline__ void pace_by_progress(const unsigned long long *steps
         __builtin_amdgcn_s_setprio(1);
 }
 
+// Column range of every trace of CMPs c_lo..c_hi that a window may read for
+// any candidate in the boxes of the samples t_start + m stride (m < ns) at
+// output CMP j: tau^2 = (n0 + As dm)^2 + B n0 dm^2 / dt + C n0 h^2 / dt (CRS;
+// CMP: n0^2 + C h^2 / dt^2) is monotone in B and C and convex in As, so the
+// box's ends bound it; two columns of margin cover the kernel's binary32
+// rounding.  Ranges longer than TILE_STAGE_MAX are marked for direct reads.
+template <int OP, int W>
+__device__ void build_tile_table(const SearchArgs &a, int2 *tab, int32_t j, int32_t c_lo, int32_t c_hi,
+                                 int32_t t_start, int32_t ns, int32_t stride)
+{
+    const StoreView &sv = a.sv;
+    const int64_t i0 = sv.cmp_ptr[c_lo], i1 = sv.cmp_ptr[c_hi + 1];
+    const double inv_dt = 1.0 / static_cast<double>(sv.dt);
+    for (int64_t idx = threadIdx.x; idx < i1 - i0; idx += blockDim.x) {
+        const TraceMeta m = sv.meta[i0 + idx];
+        const double dm = static_cast<double>(static_cast<float>(m.cmp - j) * sv.dx);
+        const double h2 = static_cast<double>(m.h2);
+        double qlo = 1e300, qhi = -1e300;
+        for (int32_t q = 0; q < ns; ++q) {
+            const int32_t n0 = t_start + q * stride;
+            const double nd = static_cast<double>(n0);
+            const float *lo = a.lo_tab + n0 * 3, *hi = a.hi_tab + n0 * 3;
+            double mn, mx;
+            if constexpr (OP == 1) {
+                const double cc = inv_dt * inv_dt * h2;
+                mn = nd * nd + fmin(lo[0] * cc, hi[0] * cc);
+                mx = nd * nd + fmax(lo[0] * cc, hi[0] * cc);
+            } else {
+                const double e1 = nd + lo[0] * inv_dt * dm, e2 = nd + hi[0] * inv_dt * dm;
+                const double amin = e1 * e2 <= 0.0 ? 0.0 : fmin(e1 * e1, e2 * e2), amax = fmax(e1 * e1, e2 * e2);
+                const double bc = nd * inv_dt * dm * dm, cc = nd * inv_dt * h2;
+                mn = amin + fmin(lo[1] * bc, hi[1] * bc) + fmin(lo[2] * cc, hi[2] * cc);
+                mx = amax + fmax(lo[1] * bc, hi[1] * bc) + fmax(lo[2] * cc, hi[2] * cc);
+            }
+            qlo = fmin(qlo, mn);
+            qhi = fmax(qhi, mx);
+        }
+        int2 e = make_int2(0, 0);
+        if (qhi >= 0.0) {
+            const double tlo = sqrt(fmax(qlo, 0.0)), thi = fmin(sqrt(qhi), static_cast<double>(sv.nt - 1));
+            const int32_t clo = max(0, static_cast<int32_t>(floor(tlo)) + PAD - W / 2 - 2);
+            const int32_t chi = static_cast<int32_t>(floor(thi)) + PAD - W / 2 + 2;
+            const int32_t len = chi + W + 1 - clo;
+            if (len > TILE_STAGE_MAX)
+                e = make_int2(0, -1);
+            else if (len > 0)
+                e = make_int2(clo, len);
+        }
+        tab[idx] = e;
+    }
+}
+
 // Plain search: each workgroup runs the whole evolution (initial population
 // and NG generations) of its samples.  ENS: each workgroup sweeps its time
 // samples through the traces of its bucket, one trace after another: within
@@ -178,7 +241,7 @@ __device__ __forceinline__ void pace_by_progress(const unsigned long long *steps
 // exploitation stages.  KIND selects the counters and names the kernel.
 // k_search_dense is the same code held to 64 VGPRs (8 waves per SIMD), for
 // launches whose wave count fits the chip in one round at that occupancy.
-template <int OP, int DT, int W, int KIND, bool ADAPT>
+template <int OP, int DT, int W, int KIND, bool ADAPT, bool TILES = false>
 __device__ __forceinline__ void search_body(const SearchArgs &a)
 {
     extern __shared__ float lds[];
@@ -218,6 +281,17 @@ __device__ __forceinline__ void search_body(const SearchArgs &a)
     uint32_t n_ev = 0;
     uint64_t sum_m = 0;
     float pbest[3] = {0.f, 0.f, 0.f};  // this sample's best on the previous trace of the sweep
+    // TILES: the step's table, 16 zeros and two staging buffers per wave after
+    // the slices' merge area
+    TileCtx tc{nullptr, 0, nullptr, nullptr};
+    if constexpr (TILES) {
+        float *base = lds + (nsl > 1 ? 2 * nsl * (W + 2) * WAVE : 0);
+        float *zero = base + 2 * a.tile_cap;
+        if (threadIdx.x < 16) zero[threadIdx.x] = 0.0f;
+        tc.tab = reinterpret_cast<const int2 *>(base);
+        tc.zero8 = zero;
+        tc.stage = zero + 16 + wave * 2 * (TILE_STAGE_MAX + 8);
+    }
 
     for (int32_t k = k_begin; k < k_end; ++k) {
         if (a.progress) pace_by_progress(a.progress, k - k_begin);
@@ -228,6 +302,12 @@ __device__ __forceinline__ void search_body(const SearchArgs &a)
         const uint64_t sid =
             static_cast<uint64_t>(n0) + static_cast<uint64_t>(a.sv.nt) * static_cast<uint64_t>(j);
         const int64_t here = static_cast<int64_t>(o) * a.n_t + tt;
+        if constexpr (TILES) {
+            __syncthreads();   // every wave is done with the previous step's table
+            build_tile_table<OP, W>(a, const_cast<int2 *>(tc.tab), j, c_lo, c_hi, t_start, ns, stride);
+            tc.i0 = static_cast<int32_t>(a.sv.cmp_ptr[c_lo]);
+            __syncthreads();
+        }
 
         // initial population (section "Initializing") and ENS seeds
         float x[3] = {0.f, 0.f, 0.f};
@@ -263,7 +343,7 @@ __device__ __forceinline__ void search_body(const SearchArgs &a)
         }
         {
             const Cand<float> cand = make_cand<OP, float>(x, n0, j, ap, a.sv.nt, a.sv.dt, a.sv.dx);
-            const float Sev = eval_slices<DT, W>(a.sv, cand, c_lo, c_hi, wave, nsl, lane, lds, buf, M);
+            const float Sev = eval_slices<DT, W, TILES>(a.sv, cand, c_lo, c_hi, wave, nsl, lane, lds, buf, M, tc);
             if (!scored) {
                 S = Sev;
                 if (live) {
@@ -294,7 +374,7 @@ __device__ __forceinline__ void search_body(const SearchArgs &a)
                 make_trial<OP>(x, S, base, np, slot, w, a.F, a.cr_thr, lo, hi, u);
             }
             const Cand<float> cand = make_cand<OP, float>(u, n0, j, ap, a.sv.nt, a.sv.dt, a.sv.dx);
-            const float St = eval_slices<DT, W>(a.sv, cand, c_lo, c_hi, wave, nsl, lane, lds, buf, M);
+            const float St = eval_slices<DT, W, TILES>(a.sv, cand, c_lo, c_hi, wave, nsl, lane, lds, buf, M, tc);
             if (live) {
                 n_ev += 1;
                 sum_m += static_cast<uint64_t>(M);
@@ -517,6 +597,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     search_body<OP, DT, W, KIND, false>(a);
 }
 
+// the same search with the windows of binary32 rows staged per trace in LDS
+// (ens_tuning.gather = 1): bit for bit the results of k_search
+template <int OP, int W, int KIND>
+__global__ __launch_bounds__(512) void k_search_tiles(SearchArgs a)
+{
+    search_body<OP, DT_F32, W, KIND, false, true>(a);
+}
+
 // the same search with JADE's control-parameter adaptation and archive
 template <int OP, int DT, int W, int KIND>
 __global__ __launch_bounds__(512) void k_search_jade(SearchArgs a)
@@ -542,7 +630,23 @@ hipError_t launch_search_dt(int op, int window, int kind, int dense, const Searc
         }
         return hipGetLastError();
     }
-    const size_t lds = a.nsl > 1 ? sizeof(float) * 2 * a.nsl * (window + 2) * WAVE : 0;
+    size_t lds = a.nsl > 1 ? sizeof(float) * 2 * a.nsl * (window + 2) * WAVE : 0;
+    if (a.tiles) {
+        if constexpr (DT != DT_F32) {
+            return hipErrorInvalidValue;
+        } else {
+            if (a.adapt) return hipErrorInvalidValue;
+            lds += sizeof(float) * (2 * static_cast<size_t>(a.tile_cap) + 16 + 2 * a.nsl * (TILE_STAGE_MAX + 8));
+            if (kind == 0) {
+                ENS_DISPATCH_OP(op, ENS_DISPATCH_W(window,
+                    hipLaunchKernelGGL((k_search_tiles<OP, W, 0>), grid, block, lds, s, a)));
+            } else {
+                ENS_DISPATCH_OP(op, ENS_DISPATCH_W(window,
+                    hipLaunchKernelGGL((k_search_tiles<OP, W, 1>), grid, block, lds, s, a)));
+            }
+            return hipGetLastError();
+        }
+    }
     if (a.adapt && kind == 0) {
         ENS_DISPATCH_OP(op, ENS_DISPATCH_W(window,
             hipLaunchKernelGGL((k_search_jade<OP, DT, W, 0>), grid, block, lds, s, a)));

@@ -41,7 +41,7 @@ def test_struct_sizes_match_header_layout():
     assert C.sizeof(ens.DeCfg) == 68
     assert C.sizeof(ens.Result) == 56
     assert C.sizeof(ens.Stats) == 176
-    assert C.sizeof(ens.Tuning) == 28
+    assert C.sizeof(ens.Tuning) == 32
 
 
 def test_struct_sizes_match_the_c_compiler(tmp_path):
