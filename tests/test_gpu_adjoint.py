@@ -117,3 +117,55 @@ def test_polish_matches_oracle_polish_from_the_same_start(ens, name, store, n_cm
     # step the binary64 one does not)
     assert abs(S_gpu_at.mean() - S_or.mean()) <= 0.02 * gain_or.mean() + 1e-6
     assert same_acc >= 0.9
+
+
+def test_adjoint_matches_central_differences_of_the_device_objective(ens):
+    """semblance_backward against central differences of the device's own
+    binary64 re-score of the same binary32 traces.  The interpolated
+    semblance has a kink wherever a trace's traveltime crosses a whole sample,
+    and with up to 816 traces per candidate a step of 1e-4 of the box span
+    straddles one in 96% of the candidates (the oracle's quotients); the
+    quotient also divides the re-score's rounding (up to about 1e-11) by the
+    step, which rules out steps much below 1e-5.  The step is 1e-5 of the
+    span, and a quotient counts as a derivative only where S is smooth over
+    [p - h, p + h]: pairs where the oracle's own quotient departs from its
+    analytic gradient by more than 1e-5 are excluded and counted, as are the
+    pairs the per-element test excludes (a trace within the binary32
+    traveltime error of a whole sample, where the adjoint may take the other
+    side's slope, or within 0.05 samples of a participation edge)."""
+    ctx, g, wl, L = _setup(ens, "crs_ens", "f32", 48)
+    bounds = base_bounds(wl)
+    cmp, t, p = random_candidates(2000, g.n_cmp, g.nt, g.dt, 3, bounds, seed=23, t_range=(20, g.nt))
+    span = np.stack([np.subtract(*L.sample_bounds(bounds, tt)[::-1]) for tt in t]).astype(np.float64)
+    dS = np.ones(cmp.size, np.float32)
+    g_gpu = ctx.semblance_backward(_dev(cmp), _dev(t), _dev(p), _dev(dS)).cpu().numpy().astype(np.float64)
+    _, g_or = L.semblance_grad(cmp, t, p.astype(np.float64))
+    keep = np.ones(cmp.size, bool)
+    fd_gpu = np.zeros((cmp.size, 3))
+    for d in range(3):
+        h = (1e-5 * span[:, d]).astype(np.float32)
+        pp, pm = p.copy(), p.copy()
+        pp[:, d] = p[:, d] + h
+        pm[:, d] = p[:, d] - h
+        step = pp[:, d].astype(np.float64) - pm[:, d].astype(np.float64)
+        Sp = ctx.semblance_eval64(_dev(cmp), _dev(t), _dev(pp)).cpu().numpy()
+        Sm = ctx.semblance_eval64(_dev(cmp), _dev(t), _dev(pm)).cpu().numpy()
+        fd_gpu[:, d] = (Sp - Sm) / step
+        Sp_or, _, _ = L.semblance(cmp, t, pp.astype(np.float64))
+        Sm_or, _, _ = L.semblance(cmp, t, pm.astype(np.float64))
+        fd_or = (Sp_or - Sm_or) / step
+        scale_or = np.maximum(np.abs(g_or[:, d]), np.median(np.abs(g_or[:, d])))
+        keep &= np.abs(fd_or - g_or[:, d]) <= 1e-5 * scale_or
+    smooth = keep.copy()
+    _, _, margin = L.semblance(cmp, t, p.astype(np.float64))
+    keep &= (margin >= EDGE) & (L.kink_margin(cmp, t, p.astype(np.float64)) >= KINK)
+    print(f"central differences: {cmp.size} pairs, {(~smooth).sum()} excluded where S is not smooth "
+          f"over the step, {(smooth & ~keep).sum()} at an edge or within rounding of a kink; "
+          f"{keep.sum()} compared")
+    assert keep.sum() >= 1000
+    for d in range(3):
+        gz, fz = g_gpu[keep, d] * span[keep, d], fd_gpu[keep, d] * span[keep, d]
+        scale = np.maximum(np.abs(fz), np.median(np.abs(fz)))
+        rel = np.abs(gz - fz) / scale
+        print(f"  d={d}: max rel {rel.max():.2e}, 99% {np.quantile(rel, 0.99):.2e}")
+        assert rel.max() <= REL, f"d={d}: worst pair {np.argmax(rel)} rel {rel.max():.3e}"
