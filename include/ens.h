@@ -340,9 +340,9 @@ ens_status semblance_backward(ens_ctx *ctx, const ens_candidates *cands, const f
 ens_status ens_stack(ens_ctx *ctx, const ens_t0_grid *t0_grid, const float *params, float *stack_out,
                      const float *S, double *coherence_rms);
 
-/* ens_stack for callers that cannot allocate device memory (code under HIP
- * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
- * same outputs from the same kernels, with the output-CMP list and the
+/* ens_stack for callers that cannot allocate device memory (tight serving
+ * loops, harnesses that forbid hipMalloc): the same outputs from the same
+ * kernels, with the output-CMP list and the
  * coherence RMS kept in a static per-device scratch array of 256 B + 4 B x
  * ENS_NOALLOC_MAX_CMPS (held by each GPU the library runs on until the
  * process ends) instead of context workspace.  No hipMalloc, hipFree or
@@ -350,7 +350,9 @@ ens_status ens_stack(ens_ctx *ctx, const ens_t0_grid *t0_grid, const float *para
  * (more: ENS_E_RANGE, nothing launched).  Every call on one GPU uses that
  * GPU's one array, so calls that overlap on a GPU (from other contexts,
  * threads or streams) race; calls ordered on one stream do not.  Waits for
- * the stream before returning.  Arguments and errors otherwise as ens_stack. */
+ * the stream before returning (the RMS is returned on the host), so it is
+ * not meant to be recorded into a stream capture.  Arguments and errors
+ * otherwise as ens_stack. */
 enum { ENS_NOALLOC_MAX_CMPS = 65536 };
 ens_status ens_stack_noalloc(ens_ctx *ctx, const ens_t0_grid *t0_grid, const float *params, float *stack_out,
                              const float *S, double *coherence_rms);
