@@ -196,7 +196,10 @@ class Context:
 
     def set_tuning(self, waves_per_sample_group=0, use_graph=0, collect_timing=0, item_order=0,
                    occupancy=0, packing=0, gather=0):
-        """Launch shape of the search kernels; 0 = chosen by measurement."""
+        """Launch shape of the search kernels (ens_tuning): slices, HIP-graph
+        replay, per-launch timing, item order, register budget, packed
+        exploration width (1: off) and LDS-staged binary32 windows (gather=1);
+        0 = chosen by measurement (gather: direct reads)."""
         t = _sized(Tuning, waves_per_sample_group=waves_per_sample_group, use_graph=use_graph,
                    collect_timing=collect_timing, item_order=item_order, occupancy=occupancy,
                    packing=packing, gather=gather)
