@@ -2,7 +2,8 @@
 consecutive samples laid end to end over 2, 4 or 8 waves give the same
 search as one population per lane group, bit for bit, on uneven populations
 (NP 16 -> 64 with t, so that populations straddle waves), for the plain
-search, ENS stage 0 with exchange and with time-sample skipping, and
+search, ENS stage 0 with exchange and with time-sample skipping (N_skip 1
+and 2), on binary32, binary16 and bfloat16 rows, and
 through the measured launch shape (against the fixed shape it picks)."""
 import numpy as np
 import pytest
@@ -33,16 +34,16 @@ def _same(a, b):
     assert a["n_evals"] == b["n_evals"] and a["sum_m"] == b["sum_m"]
 
 
-@pytest.mark.parametrize("store", ["f32", "f16"])
-@pytest.mark.parametrize("mode", ["plain", "ens", "ens_skip1"])
+@pytest.mark.parametrize("store", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("mode", ["plain", "ens", "ens_skip1", "ens_skip2"])
 def test_packed_exploration_equals_one_population_per_lane_group(ens, mode, store):
     g, wl = make_workload("crs_uneven", n_cmp=20, nt=400)
     ctx = _ctx(ens, g, wl, store)
     de = dict(wl["de"], np_lo=16, np_hi=64, ng_f=4, ng_bf=1, n_bucket=6)
     if mode == "plain":
         de["ens_enabled"] = 0
-    if mode == "ens_skip1":
-        de["n_skip"] = 1
+    if mode.startswith("ens_skip"):
+        de["n_skip"] = int(mode[-1])
     # t from 37 (a ragged start) to 391: populations of 17..63 members
     kw = dict(seed=11, t_begin=37, t_end=391)
     ctx.set_tuning(waves_per_sample_group=1, item_order=1, occupancy=1, packing=1)
