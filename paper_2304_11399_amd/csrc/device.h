@@ -333,21 +333,24 @@ __device__ __forceinline__ void accum_trace(Acc<W, R> &acc, const Cand<R> &c, co
 // A VALU instruction may read the result of v_dot2_f32_f16 only three wait
 // states after it.  The compiler counts them for its own instructions but not
 // for inline assembly, so every dot result passes through one s_nop 2 (three
-// wait states) before anything reads it.
+// wait states) before anything reads it.  The statement is not volatile: its
+// operands order it after the dots and before every reader, and a volatile
+// statement would also stop the scheduler from moving the next trace's load
+// above it.
 template <int W>
 __device__ __forceinline__ void dot_results_ready(float *a)
 {
     static_assert(W % 2 == 1 && W >= 3 && W <= 15, "odd window, 3..15");
     if constexpr (W == 3) {
-        asm volatile("s_nop 2" : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]));
+        asm("s_nop 2" : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]));
     } else if constexpr (W == 5) {
-        asm volatile("s_nop 2" : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(a[4]));
+        asm("s_nop 2" : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(a[4]));
     } else if constexpr (W == 7) {
-        asm volatile("s_nop 2" : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(a[4]), "+v"(a[5]),
+        asm("s_nop 2" : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(a[4]), "+v"(a[5]),
                      "+v"(a[6]));
     } else {
         // longer windows: the first seven, then the rest
-        asm volatile("s_nop 2" : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(a[4]), "+v"(a[5]),
+        asm("s_nop 2" : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(a[4]), "+v"(a[5]),
                      "+v"(a[6]));
         dot_results_ready<W - 6>(a + 6);
     }
