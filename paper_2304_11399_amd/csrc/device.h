@@ -90,43 +90,65 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_buffer(const void *row, ui
 // always N/2 aligned dwords.  The loads are raw buffer loads with the row in
 // scalar registers and a 32-bit lane offset.
 template <int DT, int N>
-__device__ __forceinline__ void load_window(const typename Store<DT>::T *__restrict__ row, uint32_t off,
-                                            uint32_t copy1, uint32_t row_bytes, float *u)
+struct RawWindow {
+    uint32_t d[DT == DT_F32 ? N : N / 2];
+};
+
+template <int DT, int N>
+__device__ __forceinline__ RawWindow<DT, N> load_window_raw(const typename Store<DT>::T *__restrict__ row,
+                                                           uint32_t off, uint32_t copy1, uint32_t row_bytes)
 {
+    RawWindow<DT, N> r;
     const __amdgpu_buffer_rsrc_t rs = row_buffer(row, row_bytes);
     if constexpr (DT == DT_F32) {
         int k = 0;
 #pragma unroll
         for (; k + 4 <= N; k += 4) {
             const u4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 4u * k, 0, 0);
-            u[k] = __uint_as_float(v.x); u[k + 1] = __uint_as_float(v.y);
-            u[k + 2] = __uint_as_float(v.z); u[k + 3] = __uint_as_float(v.w);
+            r.d[k] = v.x; r.d[k + 1] = v.y; r.d[k + 2] = v.z; r.d[k + 3] = v.w;
         }
         if constexpr (N % 4 >= 2) {
             const u2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, off + 4u * k, 0, 0);
-            u[k] = __uint_as_float(v.x); u[k + 1] = __uint_as_float(v.y);
+            r.d[k] = v.x; r.d[k + 1] = v.y;
             k += 2;
         }
-        if constexpr (N % 2 == 1) u[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, off + 4u * k, 0, 0));
+        if constexpr (N % 2 == 1) r.d[k] = __builtin_amdgcn_raw_buffer_load_b32(rs, off + 4u * k, 0, 0);
     } else {
         static_assert(N % 2 == 0, "16-bit windows hold an even number of samples");
         constexpr int ND = N / 2;
         const uint32_t start = off + (off & 2u) * (copy1 - 1u);
-        uint32_t d[ND];
         int k = 0;
 #pragma unroll
         for (; k + 4 <= ND; k += 4) {
             const u4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, start + 4u * k, 0, 0);
-            d[k] = v.x; d[k + 1] = v.y; d[k + 2] = v.z; d[k + 3] = v.w;
+            r.d[k] = v.x; r.d[k + 1] = v.y; r.d[k + 2] = v.z; r.d[k + 3] = v.w;
         }
 #pragma unroll
-        for (; k < ND; ++k) d[k] = __builtin_amdgcn_raw_buffer_load_b32(rs, start + 4u * k, 0, 0);
+        for (; k < ND; ++k) r.d[k] = __builtin_amdgcn_raw_buffer_load_b32(rs, start + 4u * k, 0, 0);
+    }
+    return r;
+}
+
+template <int DT, int N>
+__device__ __forceinline__ void unpack_window(const RawWindow<DT, N> &r, float *u)
+{
+    if constexpr (DT == DT_F32) {
 #pragma unroll
-        for (int m = 0; m < ND; ++m) {
-            u[2 * m] = half_to_f32(d[m] & 0xffffu, DT);
-            u[2 * m + 1] = half_to_f32(d[m] >> 16, DT);
+        for (int k = 0; k < N; ++k) u[k] = __uint_as_float(r.d[k]);
+    } else {
+#pragma unroll
+        for (int m = 0; m < N / 2; ++m) {
+            u[2 * m] = half_to_f32(r.d[m] & 0xffffu, DT);
+            u[2 * m + 1] = half_to_f32(r.d[m] >> 16, DT);
         }
     }
+}
+
+template <int DT, int N>
+__device__ __forceinline__ void load_window(const typename Store<DT>::T *__restrict__ row, uint32_t off,
+                                            uint32_t copy1, uint32_t row_bytes, float *u)
+{
+    unpack_window<DT, N>(load_window_raw<DT, N>(row, off, copy1, row_bytes), u);
 }
 
 // The per-line tables (CMP offsets, trace geometry, scales) stay unchanged
@@ -294,14 +316,30 @@ __device__ __forceinline__ TT<R> traveltime(const Cand<R> &c, const CmpTerm<R> &
     return r;
 }
 
-// Accumulate one trace into the window sums.  row: the padded trace row,
-// row_bytes long.
-template <int DT, int W, bool SCALED, typename R>
-__device__ __forceinline__ void accum_trace(Acc<W, R> &acc, const Cand<R> &c, const CmpTerm<R> &ct,
-                                            R h2, const typename Store<DT>::T *__restrict__ row,
-                                            uint32_t copy1, uint32_t row_bytes, float scale)
+// One trace's window in two halves, so that a caller can issue the loads of
+// two traces before it uses either: the traveltime and the window load, then
+// the interpolation and the sums.  row: the padded trace row, row_bytes long.
+template <int DT, int W, typename R>
+struct TraceWindow {
+    TT<R> tt;
+    RawWindow<DT, W + 1> raw;
+};
+
+template <int DT, int W, typename R>
+__device__ __forceinline__ TraceWindow<DT, W, R> trace_window(const Cand<R> &c, const CmpTerm<R> &ct, R h2,
+                                                              const typename Store<DT>::T *__restrict__ row,
+                                                              uint32_t copy1, uint32_t row_bytes)
 {
-    const TT<R> tt = traveltime<W, sizeof(typename Store<DT>::T)>(c, ct, h2);
+    TraceWindow<DT, W, R> r;
+    r.tt = traveltime<W, sizeof(typename Store<DT>::T)>(c, ct, h2);
+    r.raw = load_window_raw<DT, W + 1>(row, r.tt.off, copy1, row_bytes);
+    return r;
+}
+
+template <int DT, int W, bool SCALED, typename R>
+__device__ __forceinline__ void trace_accumulate(Acc<W, R> &acc, const TraceWindow<DT, W, R> &tw, float scale)
+{
+    const TT<R> &tt = tw.tt;
     R wb = tt.f;
     R wa = R(1) - tt.f;
     if constexpr (SCALED) {
@@ -310,7 +348,7 @@ __device__ __forceinline__ void accum_trace(Acc<W, R> &acc, const Cand<R> &c, co
     }
     acc.M += tt.ok ? 1 : 0;
     float u[W + 1];
-    load_window<DT, W + 1>(row, tt.off, copy1, row_bytes, u);
+    unpack_window<DT, W + 1>(tw.raw, u);
 #pragma unroll
     for (int k = 0; k < W; ++k) {
         // binary32 samples in binary32: u_k + f (u_k+1 - u_k), a difference
@@ -328,6 +366,14 @@ __device__ __forceinline__ void accum_trace(Acc<W, R> &acc, const Cand<R> &c, co
         acc.s[k] += a;
         acc.E = fmadd(a, a, acc.E);
     }
+}
+
+template <int DT, int W, bool SCALED, typename R>
+__device__ __forceinline__ void accum_trace(Acc<W, R> &acc, const Cand<R> &c, const CmpTerm<R> &ct,
+                                            R h2, const typename Store<DT>::T *__restrict__ row,
+                                            uint32_t copy1, uint32_t row_bytes, float scale)
+{
+    trace_accumulate<DT, W, SCALED, R>(acc, trace_window<DT, W, R>(c, ct, h2, row, copy1, row_bytes), scale);
 }
 
 // A VALU instruction may read the result of v_dot2_f32_f16 only three wait
@@ -369,14 +415,24 @@ __device__ __forceinline__ void dot_results_ready(float *a)
 // taken with alignbit.  A trace that does not take part (q < 0, tau > nt - 1,
 // outside the aperture) gets zero weights, which also clears whatever the
 // window load returned.
+// One trace's binary16 window in two halves, so that a caller can issue the
+// loads of two traces before it uses either: the traveltime, the weights and
+// the window load, then the dot products and the sums.
 template <int W>
-__device__ __forceinline__ void accum_trace_f16(Acc<W, float> &acc, const CmpTerm<float> &ct, float ga, float h2,
-                                                const uint16_t *__restrict__ row, uint32_t copy1, uint32_t row_bytes,
-                                                uint32_t wsc, const float kq, uint32_t bbits, uint32_t shift,
-                                                float tau_max)
+struct F16Window {
+    uint32_t d[(W + 1) / 2];
+    uint32_t wbits;
+};
+
+template <int W>
+__device__ __forceinline__ F16Window<W> f16_window(Acc<W, float> &acc, const CmpTerm<float> &ct, float ga, float h2,
+                                                   const uint16_t *__restrict__ row, uint32_t copy1,
+                                                   uint32_t row_bytes, uint32_t wsc, const float kq, uint32_t bbits,
+                                                   uint32_t shift, float tau_max)
 {
     typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
     constexpr int ND = (W + 1) / 2;
+    F16Window<W> r;
     const float q = fmadd(ga, h2, ct.Q);
     const float tau = fast_sqrt(q);
     const bool ok = ct.in_ap && tau <= tau_max;   // false for a NaN (q < 0)
@@ -388,29 +444,35 @@ __device__ __forceinline__ void accum_trace_f16(Acc<W, float> &acc, const CmpTer
     const uint32_t start = off + __umul24(off & 2u, copy1 - 1u);
     half2_t w = __builtin_bit_cast(half2_t, __builtin_amdgcn_cvt_pkrtz(wa, wb));
     w = w * __builtin_bit_cast(half2_t, wsc);
-    const uint32_t wbits = ok ? __builtin_bit_cast(uint32_t, w) : 0u;
+    r.wbits = ok ? __builtin_bit_cast(uint32_t, w) : 0u;
     acc.M += ok ? 1 : 0;
     const __amdgpu_buffer_rsrc_t rs = row_buffer(row, row_bytes);
-    uint32_t d[ND];
     int m = 0;
 #pragma unroll
     for (; m + 4 <= ND; m += 4) {
         const u4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, start + 4u * m, 0, 0);
-        d[m] = v.x; d[m + 1] = v.y; d[m + 2] = v.z; d[m + 3] = v.w;
+        r.d[m] = v.x; r.d[m + 1] = v.y; r.d[m + 2] = v.z; r.d[m + 3] = v.w;
     }
     if constexpr (ND % 4 >= 2) {
         const u2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, start + 4u * m, 0, 0);
-        d[m] = v.x; d[m + 1] = v.y;
+        r.d[m] = v.x; r.d[m + 1] = v.y;
         m += 2;
     }
-    if constexpr (ND % 2 == 1) d[m] = __builtin_amdgcn_raw_buffer_load_b32(rs, start + 4u * m, 0, 0);
+    if constexpr (ND % 2 == 1) r.d[m] = __builtin_amdgcn_raw_buffer_load_b32(rs, start + 4u * m, 0, 0);
+    return r;
+}
+
+template <int W>
+__device__ __forceinline__ void f16_accumulate(Acc<W, float> &acc, const F16Window<W> &win)
+{
     float a[W];
 #pragma unroll
     for (int k = 0; k < W; ++k) {
-        const uint32_t pr = (k & 1) ? __builtin_amdgcn_alignbit(d[k / 2 + 1], d[k / 2], 16) : d[k / 2];
+        const uint32_t pr =
+            (k & 1) ? __builtin_amdgcn_alignbit(win.d[k / 2 + 1], win.d[k / 2], 16) : win.d[k / 2];
         // the three-operand form with an inline zero (the two-operand form the
         // compiler picks for a zero accumulator costs a register clear each)
-        asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(a[k]) : "v"(pr), "v"(wbits));
+        asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(a[k]) : "v"(pr), "v"(win.wbits));
     }
     dot_results_ready<W>(a);
 #pragma unroll
@@ -418,6 +480,15 @@ __device__ __forceinline__ void accum_trace_f16(Acc<W, float> &acc, const CmpTer
         acc.s[k] += a[k];
         acc.E = fmadd(a[k], a[k], acc.E);
     }
+}
+
+template <int W>
+__device__ __forceinline__ void accum_trace_f16(Acc<W, float> &acc, const CmpTerm<float> &ct, float ga, float h2,
+                                                const uint16_t *__restrict__ row, uint32_t copy1, uint32_t row_bytes,
+                                                uint32_t wsc, const float kq, uint32_t bbits, uint32_t shift,
+                                                float tau_max)
+{
+    f16_accumulate<W>(acc, f16_window<W>(acc, ct, ga, h2, row, copy1, row_bytes, wsc, kq, bbits, shift, tau_max));
 }
 
 template <int W, typename R>

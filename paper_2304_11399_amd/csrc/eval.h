@@ -94,11 +94,16 @@ __device__ __forceinline__ void accumulate_cmps(const StoreView &sv, const Cand<
             const int32_t i1 = static_cast<int32_t>(cmp_ptr[c + 1]);
             int32_t i = static_cast<int32_t>(cmp_ptr[c]) + first;
             for (; i + step < i1; i += 2 * step) {
+                // both windows' loads are in flight before either is used
                 const int32_t i2 = i + step;
-                accum_trace_f16<W>(acc, ct, cand.ga, meta[i].h2, store + static_cast<size_t>(i) * sv.ld, sv.copy1,
-                                   row_bytes, wsc[i], kq, bbits, shift, tau_max);
-                accum_trace_f16<W>(acc, ct, cand.ga, meta[i2].h2, store + static_cast<size_t>(i2) * sv.ld,
-                                   sv.copy1, row_bytes, wsc[i2], kq, bbits, shift, tau_max);
+                const F16Window<W> w1 = f16_window<W>(acc, ct, cand.ga, meta[i].h2,
+                                                      store + static_cast<size_t>(i) * sv.ld, sv.copy1, row_bytes,
+                                                      wsc[i], kq, bbits, shift, tau_max);
+                const F16Window<W> w2 = f16_window<W>(acc, ct, cand.ga, meta[i2].h2,
+                                                      store + static_cast<size_t>(i2) * sv.ld, sv.copy1, row_bytes,
+                                                      wsc[i2], kq, bbits, shift, tau_max);
+                f16_accumulate<W>(acc, w1);
+                f16_accumulate<W>(acc, w2);
             }
             if (i < i1)
                 accum_trace_f16<W>(acc, ct, cand.ga, meta[i].h2, store + static_cast<size_t>(i) * sv.ld, sv.copy1,
@@ -111,13 +116,14 @@ __device__ __forceinline__ void accumulate_cmps(const StoreView &sv, const Cand<
         const int32_t i1 = static_cast<int32_t>(cmp_ptr[c + 1]);
         int32_t i = static_cast<int32_t>(cmp_ptr[c]) + first;
         for (; i + step < i1; i += 2 * step) {
+            // both windows' loads are in flight before either is used
             const int32_t i2 = i + step;
-            accum_trace<DT, W, SCALED>(acc, cand, ct, h2_of<R>(meta, i),
-                                       store + static_cast<size_t>(i) * sv.ld, sv.copy1, row_bytes,
-                                       SCALED ? scale[i] : 1.0f);
-            accum_trace<DT, W, SCALED>(acc, cand, ct, h2_of<R>(meta, i2),
-                                       store + static_cast<size_t>(i2) * sv.ld, sv.copy1, row_bytes,
-                                       SCALED ? scale[i2] : 1.0f);
+            const TraceWindow<DT, W, R> w1 = trace_window<DT, W, R>(
+                cand, ct, h2_of<R>(meta, i), store + static_cast<size_t>(i) * sv.ld, sv.copy1, row_bytes);
+            const TraceWindow<DT, W, R> w2 = trace_window<DT, W, R>(
+                cand, ct, h2_of<R>(meta, i2), store + static_cast<size_t>(i2) * sv.ld, sv.copy1, row_bytes);
+            trace_accumulate<DT, W, SCALED, R>(acc, w1, SCALED ? scale[i] : 1.0f);
+            trace_accumulate<DT, W, SCALED, R>(acc, w2, SCALED ? scale[i2] : 1.0f);
         }
         if (i < i1)
             accum_trace<DT, W, SCALED>(acc, cand, ct, h2_of<R>(meta, i),
