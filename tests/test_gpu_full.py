@@ -2,8 +2,9 @@
 computes one by one: the uneven batch (NP 16 to 64, aperture 2 to 16), the
 binary16 / bfloat16 storage line, the binary16 + polish line, and the CRS +
 ENS line with JADE and with N_skip = 2, each in the launch configuration the
-benchmark times (one fixed shape here, so that no shape-measuring launches are
-needed)."""
+benchmark times: the launch shapes come from the library's committed shape
+file, as in the benchmark (a copy of it, so that a device it has no line for
+measures its shapes without touching the committed file)."""
 import os
 
 import numpy as np
@@ -28,6 +29,12 @@ def ens():
     return e
 
 
+def _shape(ctx):
+    st = ctx.stats()
+    return {k: {f: st[k].get(f) for f in ("waves", "item_order", "dense", "packed")}
+            for k in ("explore", "exploit")}, st["tune_ms"]
+
+
 def _expected_evals(de, g):
     if de["np_lo"] == de["np_hi"]:
         return evals_ens(g.n_cmp * g.nt, de["np_lo"], de["ng_f"], de["np_bf"], de["ng_bf"],
@@ -46,14 +53,14 @@ def _gap(name, S64, g):
 
 @pytest.mark.parametrize("name,store", [("crs_uneven", "f32"), ("crs_precision", "f16"),
                                         ("crs_precision", "bf16"), ("crs_diff", "f16")])
-def test_full_size_workload(ens, name, store):
+def test_full_size_workload(ens, bench_shapes, name, store):
     g, wl = make_workload(name)
     ctx = ens.Context()
     ctx.bind(torch.from_numpy(g.traces).cuda(), g.cmp_ptr, g.offset, g.dt, g.dx, wl["op"],
              wl["window"], wl["ap_lo"], wl["ap_hi"], store=store)
-    ctx.set_tuning(waves_per_sample_group=4, item_order=1, occupancy=1)
     de = wl["de"]
     out = ctx.search(base_bounds(wl), de, seed=wl["search_seed"], keep_pre_polish=True)
+    print(f"{name} {store}: launch shapes {_shape(ctx)}")
     assert out["n_evals"] == _expected_evals(de, g)
     P_d = g.n_cmp * g.nt
     pick = np.sort(np.random.default_rng(3).choice(P_d, 1500, replace=False))
@@ -86,16 +93,16 @@ def test_full_size_workload(ens, name, store):
 
 
 @pytest.mark.parametrize("variant", ["jade", "skip2"])
-def test_full_size_crs_ens_variants(ens, variant):
+def test_full_size_crs_ens_variants(ens, bench_shapes, variant):
     # the benchmark's equal-accuracy variants at the full C2 size: JADE (R8)
     # and time-sample skipping with N_skip = 2 (R13)
     g, wl = make_workload("crs_ens")
     ctx = ens.Context()
     ctx.bind(torch.from_numpy(g.traces).cuda(), g.cmp_ptr, g.offset, g.dt, g.dx, wl["op"],
              wl["window"], wl["ap_lo"], wl["ap_hi"])
-    ctx.set_tuning(waves_per_sample_group=2, item_order=1, occupancy=1)
     de = dict(wl["de"], adapt=1, CR=0.5) if variant == "jade" else dict(wl["de"], n_skip=2)
     out = ctx.search(base_bounds(wl), de, seed=wl["search_seed"])
+    print(f"crs_ens {variant}: launch shapes {_shape(ctx)}")
     P_d = g.n_cmp * g.nt
     if variant == "jade":
         assert out["n_evals"] == evals_ens(P_d, 32, 80, 5, 1, 1, 0)

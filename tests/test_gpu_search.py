@@ -178,10 +178,14 @@ def test_polish_monotone_and_consistent(ens):
     _check_scores(dict(out, S64=None), Lq, cmp, t, 3, "polished f16", store="f16")
 
 
-def test_full_crs_ens_workload(ens):
+def test_full_crs_ens_workload(ens, bench_shapes):
+    # the full C2 line in the launch shapes the benchmark times
     ctx, g, wl, L = _setup(ens, "crs_ens")
     de, bounds = wl["de"], base_bounds(wl)
     out = ctx.search(bounds, de, seed=wl["search_seed"])
+    st = ctx.stats()
+    print("crs_ens launch shapes", {k: {f: st[k].get(f) for f in ("waves", "item_order", "dense")}
+                                    for k in ("explore", "exploit")}, "tune_ms", st["tune_ms"])
     P_d = g.n_cmp * g.nt
     assert out["n_evals"] == evals_ens(P_d, 32, 80, 5, 1, 1, 0)
     rng = np.random.default_rng(1)
