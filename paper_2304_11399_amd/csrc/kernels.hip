@@ -233,33 +233,49 @@ __device__ __forceinline__ float semblance_grad_lane(const StoreView &sv, const 
     const ENS_CONST_AS int64_t *cmp_ptr = const_view(sv.cmp_ptr);
     const ENS_CONST_AS TraceMeta *meta = const_view(sv.meta);
     const ENS_CONST_AS float *scale = const_view(sv.scale);
+    const uint32_t row_bytes = static_cast<uint32_t>(sv.ld * static_cast<int64_t>(sizeof(T)));
+    // one trace's term of dS/dp, from its window
+    auto grad_trace = [&](const TraceWindow<DT, W, float> &tw, float h2, float dm, float sc) {
+        const TT<float> &tt = tw.tt;
+        const bool use = nonzero && tt.ok && tt.tau > 0.0f;
+        float u[W + 1];
+        unpack_window<DT, W + 1>(tw.raw, u);
+        const float wa = (1.0f - tt.f) * sc, wb = tt.f * sc;
+        float dSdtau = 0.0f;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            const float a = __builtin_fmaf(wb, u[k + 1], wa * u[k]);
+            dSdtau = __builtin_fmaf(acc.s[k] - MS * a, (u[k + 1] - u[k]) * sc, dSdtau);
+        }
+        const float r = use ? coef * dSdtau / (2.0f * tt.tau) : 0.0f;
+        if constexpr (OP == 1) {
+            g[0] += r * h2 * inv_dt * inv_dt;
+        } else {
+            g[0] += r * 2.0f * (cand.n0f + cand.As * dm) * dm * inv_dt;
+            g[1] += r * cand.n0f * dm * dm * inv_dt;
+            g[2] += r * cand.n0f * h2 * inv_dt;
+        }
+    };
     for (int32_t c = c_lo; c <= c_hi; ++c) {
         const CmpTerm<float> ct = cmp_term(cand, c, sv.dx);
         const int32_t i1 = static_cast<int32_t>(cmp_ptr[c + 1]);
-        for (int32_t i = static_cast<int32_t>(cmp_ptr[c]); i < i1; ++i) {
+        int32_t i = static_cast<int32_t>(cmp_ptr[c]);
+        for (; i + 1 < i1; i += 2) {
+            // both windows' loads are in flight before either is used; the
+            // terms are added in trace order
+            const float h2a = meta[i].h2, h2b = meta[i + 1].h2;
+            const TraceWindow<DT, W, float> wa = trace_window<DT, W, float>(
+                cand, ct, h2a, store + static_cast<size_t>(i) * sv.ld, sv.copy1, row_bytes);
+            const TraceWindow<DT, W, float> wb = trace_window<DT, W, float>(
+                cand, ct, h2b, store + static_cast<size_t>(i + 1) * sv.ld, sv.copy1, row_bytes);
+            grad_trace(wa, h2a, ct.dm, scale ? scale[i] : 1.0f);
+            grad_trace(wb, h2b, ct.dm, scale ? scale[i + 1] : 1.0f);
+        }
+        if (i < i1) {
             const float h2 = meta[i].h2;
-            const TT<float> tt = traveltime<W, sizeof(T)>(cand, ct, h2);
-            const bool use = nonzero && tt.ok && tt.tau > 0.0f;
-            const float sc = scale ? scale[i] : 1.0f;
-            float u[W + 1];
-            load_window<DT, W + 1>(store + static_cast<size_t>(i) * sv.ld, tt.off, sv.copy1,
-                                   static_cast<uint32_t>(sv.ld * static_cast<int64_t>(sizeof(T))), u);
-            const float wa = (1.0f - tt.f) * sc, wb = tt.f * sc;
-            float dSdtau = 0.0f;
-#pragma unroll
-            for (int k = 0; k < W; ++k) {
-                const float a = __builtin_fmaf(wb, u[k + 1], wa * u[k]);
-                dSdtau = __builtin_fmaf(acc.s[k] - MS * a, (u[k + 1] - u[k]) * sc, dSdtau);
-            }
-            const float r = use ? coef * dSdtau / (2.0f * tt.tau) : 0.0f;
-            if constexpr (OP == 1) {
-                g[0] += r * h2 * inv_dt * inv_dt;
-            } else {
-                const float dm = ct.dm;
-                g[0] += r * 2.0f * (cand.n0f + cand.As * dm) * dm * inv_dt;
-                g[1] += r * cand.n0f * dm * dm * inv_dt;
-                g[2] += r * cand.n0f * h2 * inv_dt;
-            }
+            grad_trace(trace_window<DT, W, float>(cand, ct, h2, store + static_cast<size_t>(i) * sv.ld, sv.copy1,
+                                                  row_bytes),
+                       h2, ct.dm, scale ? scale[i] : 1.0f);
         }
     }
     return S;
