@@ -83,12 +83,13 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_buffer(const void *row, ui
                                              static_cast<int>(row_bytes), 0x00020000);
 }
 
-// Load N (even for 16-bit storage) consecutive stored samples starting at
-// byte `off` of row `row` (row_bytes long) as binary32.  16-bit rows hold a
-// second copy shifted by one sample at element copy1, so a window starting
-// at an odd element is read from that copy (element copy1 + off/2 - 1):
-// always N/2 aligned dwords.  The loads are raw buffer loads with the row in
-// scalar registers and a 32-bit lane offset.
+// N (even for 16-bit storage) consecutive stored samples starting at byte
+// `off` of row `row` (row_bytes long), as loaded (load_window_raw) and as
+// binary32 (unpack_window).  16-bit rows hold a second copy shifted by one
+// sample at element copy1, so a window starting at an odd element is read
+// from that copy (element copy1 + off/2 - 1): always N/2 aligned dwords.  The
+// loads are raw buffer loads with the row in scalar registers and a 32-bit
+// lane offset.
 template <int DT, int N>
 struct RawWindow {
     uint32_t d[DT == DT_F32 ? N : N / 2];
@@ -142,13 +143,6 @@ __device__ __forceinline__ void unpack_window(const RawWindow<DT, N> &r, float *
             u[2 * m + 1] = half_to_f32(r.d[m] >> 16, DT);
         }
     }
-}
-
-template <int DT, int N>
-__device__ __forceinline__ void load_window(const typename Store<DT>::T *__restrict__ row, uint32_t off,
-                                            uint32_t copy1, uint32_t row_bytes, float *u)
-{
-    unpack_window<DT, N>(load_window_raw<DT, N>(row, off, copy1, row_bytes), u);
 }
 
 // The per-line tables (CMP offsets, trace geometry, scales) stay unchanged
