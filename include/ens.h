@@ -83,7 +83,14 @@ typedef struct ens_ctx ens_ctx;
  *    (the exact dequantised samples are stored).  master (optional, device
  *    [n_traces][ld] binary32): the samples the binary64 re-scoring and the
  *    stack read; NULL: the dequantised samples.
- * scale and master are ignored for binary32 data.  Samples must be finite. */
+ * scale and master are ignored for binary32 data.  Samples must be finite.
+ * nt is at most 2^20; searched in binary16 (store_dtype F16) at most
+ * ENS_MAX_NT_F16: the binary16 windows round each traveltime to the grid
+ * 2^(lb-23) samples, 2^lb the smallest power of two >= max(4096, nt + 16)
+ * (2^-11 samples up to 4080 samples, 2^-10 up to 8176, 2^-9 up to 16368);
+ * longer records are refused (ENS_E_UNSUPPORTED): store them as binary32 or
+ * bfloat16, whose windows take exact traveltimes. */
+enum { ENS_MAX_NT_F16 = 16368 };
 typedef struct {
     uint32_t struct_size;
     const void *data;

@@ -21,6 +21,8 @@ LIB_PATH = os.path.join(_HERE, "libens.so")
 DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
 OPS = {"cmp": 1, "crs": 3, 1: 1, 3: 3}
 
+MAX_NT_F16 = 16368   # longest record searched in binary16 (ens.h ENS_MAX_NT_F16)
+
 ENS_OK = 0
 STATUS = {0: "ENS_OK", -1: "ENS_E_INVALID", -2: "ENS_E_RANGE", -3: "ENS_E_HIP", -4: "ENS_E_OOM",
           -5: "ENS_E_UNSUPPORTED", -6: "ENS_E_STATE"}

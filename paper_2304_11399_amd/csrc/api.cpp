@@ -392,6 +392,14 @@ ens_status ens_bind(ens_ctx *ctx, const ens_traces *tr, const ens_geometry *g, c
         return fail(ctx, ENS_E_RANGE, "ens_bind: window must be odd, 3..%d (got %d)", 2 * ENS_MAX_HALF_WINDOW + 1,
                     sem->window);
     if (sem->ap_lo < 0 || sem->ap_hi < 0) return fail(ctx, ENS_E_RANGE, "ens_bind: negative aperture");
+    // binary16 windows: the traveltime grid 2^(lb-23) samples, 2^lb >= nt + PAD, stays at or
+    // below 2^-9 samples
+    static_assert(ENS_MAX_NT_F16 + PAD == (1 << 14), "binary16 record limit");
+    if (tr->store_dtype == ENS_DTYPE_F16 && tr->nt > ENS_MAX_NT_F16)
+        return fail(ctx, ENS_E_UNSUPPORTED,
+                    "ens_bind: binary16 windows take records of at most %d samples (got %d); store longer "
+                    "records as binary32 or bfloat16",
+                    static_cast<int>(ENS_MAX_NT_F16), tr->nt);
     if (data16) {
         // the scales fold into binary16 interpolation weights exactly only as powers of two
         std::vector<float> sc(static_cast<size_t>(tr->n_traces));

@@ -1,11 +1,13 @@
 """Edge cases of the GPU search against the oracle: one-sample grids, buckets
 larger than the line, line ends, the smallest and largest populations and
-windows, the CMP operator under ENS, the record's first and last samples."""
+windows, the CMP operator under ENS, the record's first and last samples, and
+the longest records binary16 windows take."""
 import numpy as np
 import pytest
 
 import oracle
-from synth import base_bounds, make_workload
+from synth import base_bounds, make_workload, random_candidates
+from tests._tol import s_tol
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -86,3 +88,46 @@ def test_first_and_last_record_samples(ens):
     out = _run(ens, "crs_ens", dict(np_lo=16, np_hi=16, ng_f=3, n_bucket=4), (None, g_nt - 3, g_nt), 7,
                n_cmp=8, nt=g_nt)
     assert torch.isfinite(out["S"]).all()
+
+
+@pytest.mark.parametrize("nt", [4080, 6000, 12000, 16368])
+def test_long_records_in_binary16(ens, nt):
+    # the binary16 windows' traveltime grid coarsens with the record (2^-11
+    # samples up to 4080 samples, 2^-10 up to 8176, 2^-9 up to the limit of
+    # 16368); candidates over the whole record hold the tolerance of its grid
+    g, wl = make_workload("crs_ens", n_cmp=8, nt=nt)
+    ctx = ens.Context()
+    ctx.bind(torch.from_numpy(g.traces).cuda(), g.cmp_ptr, g.offset, g.dt, g.dx, wl["op"],
+             wl["window"], wl["ap_lo"], wl["ap_hi"], store="f16")
+    q, s = oracle.quantize(g.traces, "f16")
+    L = oracle.Line.from_gather(g, wl["window"], wl["op"], wl["ap_lo"], wl["ap_hi"],
+                                traces=oracle.dequantize(q, s, "f16"))
+    cmp, t, p = random_candidates(4000, g.n_cmp, g.nt, g.dt, 3, base_bounds(wl), seed=nt)
+    S, M = ctx.semblance_eval(torch.from_numpy(cmp).cuda(), torch.from_numpy(t).cuda(),
+                              torch.from_numpy(p).cuda(), with_M=True)
+    S, M = S.cpu().numpy().astype(np.float64), M.cpu().numpy()
+    S_or, M_or, margin = L.semblance(cmp, t, p.astype(np.float64))
+    flip = M != M_or
+    assert np.all(margin[flip] < 0.05) and flip.mean() < 1e-3
+    ok = ~flip
+    err = np.abs(S - S_or)[ok]
+    bound = s_tol("f16", L, cmp[ok], t[ok], p[ok])
+    print(f"nt={nt}: {cmp.size} candidates, {np.sum(t > 4096)} past sample 4096, max|dS| "
+          f"{err.max():.2e} ({np.max(err / bound):.3f} of the bound)")
+    assert np.all(err <= bound)
+
+
+def test_binary16_record_limit(ens):
+    g, wl = make_workload("crs_ens", n_cmp=2, nt=ens.MAX_NT_F16 + 1)
+    args = (torch.from_numpy(g.traces).cuda(), g.cmp_ptr, g.offset, g.dt, g.dx, wl["op"],
+            wl["window"], wl["ap_lo"], wl["ap_hi"])
+    ctx = ens.Context()
+    with pytest.raises(ens.EnsError, match="binary16 windows take records of at most 16368"):
+        ctx.bind(*args, store="f16")
+    # bfloat16 and binary32 windows take exact traveltimes: no such limit
+    for store in ("bf16", "f32"):
+        ctx.bind(*args, store=store)
+        S = ctx.semblance_eval(torch.tensor([0, 1], dtype=torch.int32).cuda(),
+                               torch.tensor([100, g.nt - 1], dtype=torch.int32).cuda(),
+                               torch.zeros(2, 3).cuda())
+        assert torch.isfinite(S).all()
