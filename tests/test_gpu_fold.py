@@ -8,7 +8,8 @@ tail only for some slice counts.  Here every loop meets empty CMPs, single
 traces and odd tails: the semblance per candidate and the adjoint per element
 against the oracle on the same stored samples, and the search in several
 launch shapes, whose every output the oracle re-scores (binary32 rows: the
-trajectories also follow the oracle's)."""
+trajectories also follow the oracle's).  Silent traces (all zeros) are the
+degenerate case of the definition (E = 0, S = 0)."""
 import dataclasses
 
 import numpy as np
@@ -157,3 +158,32 @@ def test_search_on_ragged_folds(ens, store, shape):
         print(f"  identical trajectories {same.mean():.4f}")
         assert same.mean() >= 0.95
     assert abs(S.mean() - S_run.mean()) < 2e-3
+
+
+@pytest.mark.parametrize("store", ["f32", "f16", "bf16"])
+def test_silent_traces_score_zero(ens, store):
+    # traces of zeros: E = 0, so S = 0 by definition (eq. S), with no NaN in
+    # the scores, the gradient or the search; the CMP operator reads its own
+    # CMP only, so silent CMPs score 0 for every candidate
+    g, wl = make_workload("cmp_small")
+    silent = np.array([2, 3, 4, 5, 11])
+    traces = g.traces.copy()
+    for c in silent:
+        traces[g.cmp_ptr[c]:g.cmp_ptr[c + 1]] = 0.0
+    g = dataclasses.replace(g, traces=traces)
+    ctx, L = _bind(ens, g, wl, store)
+    cmp, t, p = random_candidates(4000, g.n_cmp, g.nt, g.dt, 1, base_bounds(wl), seed=37)
+    S, M = ctx.semblance_eval(_dev(cmp), _dev(t), _dev(p), with_M=True)
+    S, M = S.cpu().numpy(), M.cpu().numpy()
+    S_or, M_or, _ = L.semblance(cmp, t, p.astype(np.float64))
+    quiet = np.isin(cmp, silent)
+    assert np.all(S[quiet] == 0.0) and np.all(S_or[quiet] == 0.0)
+    assert np.any(M[quiet] > 0)
+    gr = ctx.semblance_backward(_dev(cmp), _dev(t), _dev(p), _dev(np.ones(cmp.size, np.float32)))
+    gr = gr.cpu().numpy()
+    assert np.all(np.isfinite(gr)) and np.all(gr[quiet] == 0.0)
+    de = dict(wl["de"], np_lo=8, np_hi=8, ng_f=4)
+    out = ctx.search(base_bounds(wl), de, seed=38)
+    S_out = out["S"].cpu().numpy().reshape(g.n_cmp, -1)
+    assert np.all(np.isfinite(out["params"].cpu().numpy())) and np.all(S_out[silent] == 0.0)
+    assert np.all(out["S64"].cpu().numpy().reshape(g.n_cmp, -1)[silent] == 0.0)
