@@ -397,8 +397,9 @@ __device__ __forceinline__ void dot_results_ready(float *a)
 }
 
 // Binary16 windows through packed dot products.  The traveltime in samples
-// tau = sqrt(q) is rounded to the grid of spacing 2^-11 (B = 4096; coarser for
-// longer records) by one binary32 addition: y = tau + B + PAD - W/2 lies in
+// tau = sqrt(q) is rounded to the grid of spacing 2^-11 (B = 4096; 2^-10 and
+// 2^-9 for records of up to 8176 and 16368 samples, the longest that binary16
+// windows take) by one binary32 addition: y = tau + B + PAD - W/2 lies in
 // [B, 2B), where binary32 values are spaced by the grid.  floor(y) - B is the
 // window's first column and wb = y - floor(y), wa = 1 - wb are exact multiples
 // of the grid, hence exact in binary16, as are their products with the

@@ -264,12 +264,12 @@ __device__ __forceinline__ float semblance_grad_lane(const StoreView &sv, const 
             // both windows' loads are in flight before either is used; the
             // terms are added in trace order
             const float h2a = meta[i].h2, h2b = meta[i + 1].h2;
-            const TraceWindow<DT, W, float> wa = trace_window<DT, W, float>(
+            const TraceWindow<DT, W, float> w1 = trace_window<DT, W, float>(
                 cand, ct, h2a, store + static_cast<size_t>(i) * sv.ld, sv.copy1, row_bytes);
-            const TraceWindow<DT, W, float> wb = trace_window<DT, W, float>(
+            const TraceWindow<DT, W, float> w2 = trace_window<DT, W, float>(
                 cand, ct, h2b, store + static_cast<size_t>(i + 1) * sv.ld, sv.copy1, row_bytes);
-            grad_trace(wa, h2a, ct.dm, scale ? scale[i] : 1.0f);
-            grad_trace(wb, h2b, ct.dm, scale ? scale[i + 1] : 1.0f);
+            grad_trace(w1, h2a, ct.dm, scale ? scale[i] : 1.0f);
+            grad_trace(w2, h2b, ct.dm, scale ? scale[i + 1] : 1.0f);
         }
         if (i < i1) {
             const float h2 = meta[i].h2;
