@@ -158,3 +158,22 @@ def test_tuning_and_building_block_validation():
         assert lib.ens_quantize(h, None, 1, 1, 1, 1, None, None) == -1
     finally:
         lib.ens_ctx_destroy(h)
+
+
+def test_binary16_record_limit_is_checked_on_the_host():
+    # ens.h ENS_MAX_NT_F16, the binding's MAX_NT_F16 and the record length at
+    # which the binary16 traveltime grid would pass 2^-9 samples agree; a longer
+    # record searched in binary16 is refused before any device call
+    import re
+    src = open(os.path.join(ROOT, "include", "ens.h")).read()
+    limit = int(re.search(r"ENS_MAX_NT_F16\s*=\s*(\d+)", src).group(1))
+    assert limit == ens.MAX_NT_F16 == (1 << 14) - 16
+    from tests._tol import tau_err_f16
+    assert tau_err_f16(4080) == 1e-3 and tau_err_f16(4081) == 2e-3 and tau_err_f16(limit) == 4e-3
+    lib, h = _ctx()
+    try:
+        tr, geo, sem, keep = _bind_args(nt=limit + 1, ld=limit + 1, store_dtype=1)
+        assert lib.ens_bind(h, C.byref(tr), C.byref(geo), C.byref(sem)) == -5
+        assert b"binary16 windows take records of at most 16368" in lib.ens_last_error(h)
+    finally:
+        lib.ens_ctx_destroy(h)
