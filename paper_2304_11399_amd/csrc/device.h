@@ -430,7 +430,9 @@ __device__ __forceinline__ F16Window<W> f16_window(Acc<W, float> &acc, const Cmp
     F16Window<W> r;
     const float q = fmadd(ga, h2, ct.Q);
     const float tau = fast_sqrt(q);
-    const bool ok = ct.in_ap && tau <= tau_max;   // false for a NaN (q < 0)
+    // tau_max: the record's last sample, or -1 where the CMP lies outside the
+    // candidate's aperture; false for a NaN (q < 0)
+    const bool ok = tau <= tau_max;
     const float y = tau + kq;
     const float fl = floor_r(y);
     const float wb = y - fl;

@@ -91,6 +91,8 @@ __device__ __forceinline__ void accumulate_cmps(const StoreView &sv, const Cand<
         const uint32_t shift = sv.h16_shift;
         for (int32_t c = c_lo; c <= c_hi; ++c) {
             const CmpTerm<R> ct = cmp_term(cand, c, dx);
+            // the aperture test folded into the record test: tau <= -1 never holds
+            const float tmax = ct.in_ap ? tau_max : -1.0f;
             const int32_t i1 = static_cast<int32_t>(cmp_ptr[c + 1]);
             int32_t i = static_cast<int32_t>(cmp_ptr[c]) + first;
             for (; i + step < i1; i += 2 * step) {
@@ -98,16 +100,16 @@ __device__ __forceinline__ void accumulate_cmps(const StoreView &sv, const Cand<
                 const int32_t i2 = i + step;
                 const F16Window<W> w1 = f16_window<W>(acc, ct, cand.ga, meta[i].h2,
                                                       store + static_cast<size_t>(i) * sv.ld, sv.copy1, row_bytes,
-                                                      wsc[i], kq, bbits, shift, tau_max);
+                                                      wsc[i], kq, bbits, shift, tmax);
                 const F16Window<W> w2 = f16_window<W>(acc, ct, cand.ga, meta[i2].h2,
                                                       store + static_cast<size_t>(i2) * sv.ld, sv.copy1, row_bytes,
-                                                      wsc[i2], kq, bbits, shift, tau_max);
+                                                      wsc[i2], kq, bbits, shift, tmax);
                 f16_accumulate<W>(acc, w1);
                 f16_accumulate<W>(acc, w2);
             }
             if (i < i1)
                 accum_trace_f16<W>(acc, ct, cand.ga, meta[i].h2, store + static_cast<size_t>(i) * sv.ld, sv.copy1,
-                                   row_bytes, wsc[i], kq, bbits, shift, tau_max);
+                                   row_bytes, wsc[i], kq, bbits, shift, tmax);
         }
         return;
     }
